@@ -1,0 +1,197 @@
+/*
+ * fio.h -- C ABI of the MI355X (gfx950) library that applies a discrete
+ * Fourier integral operator by the wedge-localised method of Candes,
+ * Demanet and Ying, "Fast Computation of Fourier Integral Operators".
+ *
+ * The operator (Section 1.2, eq. (dfio)), in Egorov form a = 1 (Section 3,
+ * eq. (Egorov)):
+ *
+ *     u(x) = (Lf)(x) = (1/N) sum_{xi in Omega} exp(2 pi i Phi(x, xi)) fhat(xi),
+ *     x in X = {(n1/N, n2/N) : 0 <= n1, n2 < N},  Omega = [-N/2, N/2)^2,  N even,
+ *
+ * with fhat the 1/N-normalised DFT of f (eq. (dft)).  The apply follows the
+ * evaluation step of Section 3.4: window fhat onto angular wedges W_ell
+ * (Section 1.3), multiply by the separated frequency factors gamma^xi_{ell t},
+ * evaluate each term with a type-2 NUFFT at the warped points
+ * grad_xi Phi(x, xi_hat_ell) of a sheared, centred box, and combine with the
+ * spatial factors gamma^x_{ell t}(x) (eq. (dfioalgo)).  The factors come from
+ * the randomized separation of Section 3.3, built by fio_plan.
+ *
+ * Conventions shared by every entry point:
+ *   - Arrays are plain device pointers (HIP device memory on the device that
+ *     was current at fio_plan), complex numbers interleaved (re, im).
+ *   - fhat: N*N complex, centred: element (k1 + N/2)*N + (k2 + N/2) holds
+ *     fhat(k1, k2).  u: N*N complex, row-major: element n1*N + n2 holds
+ *     u(n1/N, n2/N).  Batches are B such arrays back to back.
+ *   - Element type: complex float (8 bytes) for FIO_F32 plans, complex
+ *     double (16 bytes) for FIO_F64 plans.
+ *   - stream: a hipStream_t passed as void*; NULL is the null stream.  Apply
+ *     calls are asynchronous and stream-ordered; the caller keeps fhat and u
+ *     alive until the stream has passed the call.  A plan owns a workspace,
+ *     so one plan must not be applied on two streams at once.
+ *   - Errors: every call returns a fio_status; nothing throws or aborts
+ *     across the ABI.  fio_last_error() returns a thread-local message for
+ *     the last failing call of this thread (valid until the next call).
+ *   - Ownership: the plan owns all device memory it allocates and frees it
+ *     in fio_destroy.  Host arrays passed in are only read during the call.
+ */
+#ifndef FIO_H
+#define FIO_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fio_plan_s *fio_plan_t;
+
+typedef enum {
+    FIO_OK = 0,
+    FIO_EINVAL = -1,    /* bad argument: odd or too small N, null pointer, tol outside (0,1), ... */
+    FIO_ENOMEM = -2,    /* device or host allocation failed */
+    FIO_EDEVICE = -3,   /* a HIP call failed (message has the HIP error string) */
+    FIO_EACCURACY = -4, /* a forced factor mode could not meet the tolerance */
+    FIO_ENOTSUP = -5    /* valid but unsupported request (e.g. amplitude kind, FP32 below its floor) */
+} fio_status;
+
+/* Phase families Phi(x, xi) = x.xi + h(x, xi), h homogeneous of degree 1 in xi.
+ * A phase must be evaluable on the device, so it is a descriptor, not a callback. */
+enum {
+    FIO_PHASE_LINEAR = 0,        /* h = p0 xi1 + p1 xi2 (translation by (p0, p1)) */
+    FIO_PHASE_WAVE = 1,          /* h = p0 |xi| (constant-speed wave, Section 1: p0 = +-c t) */
+    FIO_PHASE_ELLIPSE_C1C2 = 2,  /* h = p0 sqrt(c1^2 xi1^2 + c2^2 xi2^2), c1 = (2 + sin 2pi x1 sin 2pi x2)/16,
+                                    c2 = (2 + cos 2pi x1 cos 2pi x2)/16 (p0 = phase scale) */
+    FIO_PHASE_RADIAL = 3,        /* h = rho(x)|xi|, rho = p0 (1 + p1 sin 2pi x1) */
+    FIO_PHASE_PAPER_ELLIPSE = 4, /* Section 4, eq. (nrphase): h = p0 sqrt(r1^2 xi1^2 + r2^2 xi2^2),
+                                    r1 = (2+sin 4pi x1)(2+sin 4pi x2)/9, r2 = (2+cos 4pi x1)(2+cos 4pi x2)/9 */
+    FIO_PHASE_PAPER_CIRCLE = 5   /* eq. (circlerad): h = p0 r(x)|xi|, r = (3+sin 4pi x1)(3+sin 4pi x2)/16 */
+};
+typedef struct {
+    int kind;
+    double p[8];
+} fio_phase;
+
+/* Amplitude a(x, xi).  Only a = 1 (Egorov form) is supported; other kinds give FIO_ENOTSUP. */
+enum { FIO_AMP_ONE = 0 };
+typedef struct {
+    int kind;
+    double p[4];
+} fio_amplitude;
+
+enum { FIO_F32 = 0, FIO_F64 = 1 };
+enum { FIO_PART_EQUIANGULAR = 0, FIO_PART_CORONAE = 1 };
+enum { FIO_FACTORS_AUTO = 0, FIO_FACTORS_STORED = 1, FIO_FACTORS_LEARNED = 3 };
+
+/* Plan options.  Start from fio_default_options(); zero means "automatic" where noted. */
+typedef struct {
+    int precision;          /* FIO_F32 (default): FP32 data, FFT and combine, FP64 phase and points;
+                               FIO_F64: FP64 throughout */
+    int partition;          /* FIO_PART_EQUIANGULAR (Section 1.3) or FIO_PART_CORONAE (dyadic rings) */
+    int n_wedges;           /* equiangular wedge count L; 0 = 8 * ceil(sqrt(N) / 8) */
+    int factor_mode;        /* FIO_FACTORS_AUTO / STORED (exact separation) / LEARNED (network) */
+    unsigned long long seed;/* seed of the column/row sampling of the separation */
+    int max_batch;          /* right-hand sides processed per pass of the workspace (default 8) */
+    double sep_tol_frac;    /* separation threshold = tol * sep_tol_frac (default 0.25) */
+    double nufft_tol_frac;  /* NUFFT kernel tolerance = tol * nufft_tol_frac (default 0.1) */
+    double sigma;           /* NUFFT oversampling factor; 0 = 2.0 */
+    int kernel_width;       /* NUFFT kernel width w in fine cells; 0 = from the tolerance */
+    int r0;                 /* initial column/row sample count of the separation; 0 = 32 */
+    int verify_samples;     /* s of the s x s separation-error estimate (Section 4); 0 = 200 */
+    const void *learned;    /* fio_learned_t handle for FIO_FACTORS_LEARNED / AUTO, or NULL */
+    double learned_scale;   /* phase-scale input of the network (the family's p0) */
+} fio_options;
+
+typedef struct {
+    int N, L, precision, factor_mode, kernel_width, max_rank, min_rank, fallback;
+    double sigma, tol, plan_ms, max_sep_error;
+    long long fine_cells;      /* sum over wedges of n1*n2 */
+    long long box_cells;       /* sum over wedges of B1*B2 */
+    long long factor_bytes;    /* device bytes of stored factors */
+    long long workspace_bytes; /* device bytes of the per-batch workspace */
+    long long compressed_bytes;/* bytes of the compressed factors (V S^-1 and U_R^+, eq. (probnewfac)) */
+} fio_plan_info_t;
+
+typedef struct {
+    double theta;        /* centre angle of the wedge */
+    int members;         /* |W_ell| */
+    int rank;            /* q_ell, the separation rank */
+    int samples;         /* r, the accepted column/row sample count */
+    int M[4];            /* integer shear, row-major: xi' = M xi - xi_c (Section 3.4) */
+    int xi_c[2];         /* translation */
+    int box[2];          /* B1, B2: extent of the sheared, centred box */
+    int lo[2];           /* centred frequency of box index 0 in each axis */
+    int fine[2];         /* n1, n2: oversampled FFT grid */
+    double sep_error;    /* estimated relative separation error on a random s x s submatrix */
+} fio_wedge_info_t;
+
+void fio_default_options(fio_options *opt);
+
+/* Build a plan (Section 3.3 preprocessing: partition, shears, NUFFT set-up,
+ * randomized separation with adaptive r, factor storage).  tol is the target
+ * relative l2 error of the apply.  On success *out owns device memory. */
+fio_status fio_plan(int N, const fio_phase *phase, const fio_amplitude *amp, double tol, fio_plan_t *out);
+fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, double tol,
+                       const fio_options *opt /* nullable */, fio_plan_t *out);
+
+/* u = L fhat for one right-hand side (Section 3.4, eq. (dfioalgo)). */
+fio_status fio_apply(fio_plan_t plan, const void *fhat, void *u, void *stream);
+
+/* B right-hand sides, fhat and u holding B arrays each; the factors, warped
+ * points and kernel weights are shared across the batch. */
+fio_status fio_apply_batch(fio_plan_t plan, int B, const void *fhat, void *u, void *stream);
+
+/* n instances of possibly different N (each its own plan, all of one
+ * precision), instance i with B[i] right-hand sides at fhat[i] -> u[i] (host
+ * arrays of device pointers).  All instances and wedges run in one launch of
+ * each stage; the launch sequence is captured into a HIP graph that is
+ * replayed while the plans and pointers stay the same. */
+fio_status fio_apply_multi(int n, const fio_plan_t *plans, const void *const *fhat, void *const *u,
+                           const int *B, void *stream);
+
+/* Partial operator sum_{l0 <= ell < l1} L_ell (Section 1.3), for per-wedge checks. */
+fio_status fio_apply_wedges(fio_plan_t plan, int l0, int l1, int B, const void *fhat, void *u, void *stream);
+
+fio_status fio_plan_info(fio_plan_t plan, fio_plan_info_t *out);
+fio_status fio_wedge_info(fio_plan_t plan, int ell, fio_wedge_info_t *out);
+
+/* Host copy of the wedge id of every frequency (N*N int32, centred layout). */
+fio_status fio_wedge_map(fio_plan_t plan, int *ids_out);
+
+/* Separated factors of wedge ell evaluated in FP64 from the plan's compressed
+ * form (eq. (probnewfac)): gx[i*q + t] = gamma^x_{ell t}(x_i) for the nx flat
+ * grid indices xidx[i]; gxi[j*q + t] = gamma^xi_{ell t}(xi_j) for the nxi flat
+ * centred indices xiidx[j] (which must lie in W_ell).  Host arrays of
+ * complex double; q from fio_wedge_info.  Either side may be skipped with n = 0. */
+fio_status fio_wedge_factors(fio_plan_t plan, int ell, int nx, const long long *xidx, double *gx,
+                             int nxi, const long long *xiidx, double *gxi);
+
+/* Warped points y = grad_xi Phi(x, xi_hat_ell) (FP64, computed by the same
+ * device code the apply uses) for nx flat grid indices: y[2i], y[2i+1]. */
+fio_status fio_wedge_warp(fio_plan_t plan, int ell, int nx, const long long *xidx, double *y);
+
+/* Per-stage timing with HIP events recorded on the apply stream around each
+ * kernel launch (stage 0: window + row FFT, 1: column FFT, 2: interpolate +
+ * combine).  fio_profile(plan, 1) starts recording (and clears the totals);
+ * fio_profile_read waits for the recorded events and returns, per stage, the
+ * summed milliseconds and the number of launches.  Profiling adds one event
+ * pair per launch; it is off by default. */
+fio_status fio_profile(fio_plan_t plan, int on);
+fio_status fio_profile_read(fio_plan_t plan, double ms[3], long long launches[3]);
+
+fio_status fio_destroy(fio_plan_t plan);
+
+const char *fio_last_error(void);
+
+/* Host linear algebra of the plan, exported for CPU tests (no device use):
+ * Hermitian eigen-decomposition of an n x n complex double matrix (row-major,
+ * interleaved) by cyclic Jacobi; w: n eigenvalues in descending order, V:
+ * n x n eigenvectors as columns (row-major). */
+fio_status fio_host_eigh(int n, const double *A, double *w, double *V);
+
+/* Library version string. */
+const char *fio_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIO_H */

@@ -1,0 +1,870 @@
+// Plan construction: the preprocessing step of Section 3 for the wedge FIO.
+//
+//   1. partition Omega into angular wedges (Section 1.3) or dyadic coronae cut
+//      into angular wedges;
+//   2. per wedge, an integer shear M and translation xi_c giving a small centred
+//      box (Section 3.4), and an oversampled FFT grid for the type-2 NUFFT;
+//   3. per wedge, the randomized separation of exp(2 pi i Phi_ell) (Section 3.3):
+//      r sampled columns, their FP64 Gram matrix reduced on the GPU, a host
+//      Jacobi eigen-decomposition (the SVD of A_[C] through its Gram matrix),
+//      rank q from the singular-value threshold, r sampled rows and the
+//      pseudo-inverse U_[R]^+, the compressed form A_[C] (V S^-1) U_[R]^+ A_[R]
+//      of eq. (probnewfac), an s x s error estimate (Section 4), and adaptive
+//      doubling of r (accept when q <= r/3);
+//   4. the factors gamma^x = A_[C] V S^-1 (all x) and gamma^xi = U_[R]^+ A_[R]
+//      (all members, deconvolution and 1/N folded in) evaluated on the GPU in
+//      FP64 and stored in the plan's precision.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+
+#include "apply.hpp"
+#include "errors.hpp"
+#include "linalg.hpp"
+#include "plan_build.hpp"
+
+namespace fio {
+
+// ---------------------------------------------------------------------------
+// Partitions (host, FP64).  Same half-open rule for both: the wedge of angle
+// index k among n covers [(2k - 1) pi/n, (2k + 1) pi/n) with arg in [0, 2 pi).
+// ---------------------------------------------------------------------------
+static int angular_index(int k1, int k2, int n) {
+    double a = std::atan2((double)k2, (double)k1);
+    if (a < 0)
+        a += kTwoPi;
+    const double width = kTwoPi / n;
+    long long id = (long long)std::floor((a + M_PI / n) / width);
+    return (int)(id % n);
+}
+
+void partition_equiangular(int N, int L, std::vector<int> &ids, std::vector<double> &thetas) {
+    ids.assign((size_t)N * N, 0);
+    const int h = N / 2;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            const int k1 = i - h, k2 = j - h;
+            ids[(size_t)i * N + j] = (k1 == 0 && k2 == 0) ? 0 : angular_index(k1, k2, L);
+        }
+    thetas.resize(L);
+    for (int l = 0; l < L; ++l)
+        thetas[l] = kTwoPi * l / L;
+}
+
+// Corona 0 holds |xi| < 8 (and xi = 0); corona j >= 1 holds 2^(j+2) <= |xi| < 2^(j+3);
+// corona j is cut into n_j = 8 * 2^ceil(j/2) angular wedges.
+void partition_coronae(int N, std::vector<int> &ids, std::vector<double> &thetas) {
+    const int h = N / 2;
+    ids.assign((size_t)N * N, 0);
+    double rmax = 0;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) {
+            const double k1 = i - h, k2 = j - h;
+            rmax = std::max(rmax, std::sqrt(k1 * k1 + k2 * k2));
+        }
+    thetas.clear();
+    int base = 0;
+    for (int jc = 0;; ++jc) {
+        const double lo = jc == 0 ? 0.0 : std::ldexp(1.0, jc + 2);
+        const double hi = std::ldexp(1.0, jc + 3);
+        if (lo > rmax)
+            break;
+        const int nj = 8 << ((jc + 1) / 2);
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) {
+                const int k1 = i - h, k2 = j - h;
+                const double rad = std::sqrt((double)k1 * k1 + (double)k2 * k2);
+                if (rad >= lo && rad < hi)
+                    ids[(size_t)i * N + j] = base + angular_index(k1, k2, nj);
+            }
+        for (int k = 0; k < nj; ++k)
+            thetas.push_back(kTwoPi * k / nj);
+        base += nj;
+    }
+    ids[(size_t)h * N + h] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry of one wedge: shear among {I, lower/upper unit shears}, minimal box.
+// ---------------------------------------------------------------------------
+static const int kShears[5][4] = {{1, 0, 0, 1}, {1, 0, 1, 1}, {1, 0, -1, 1}, {1, 1, 0, 1}, {1, -1, 0, 1}};
+
+void wedge_geometry(int N, WedgeHost &W) {
+    const int h = N / 2;
+    long long best = -1;
+    for (int c = 0; c < 5; ++c) {
+        const int *M = kShears[c];
+        int mn1 = 1 << 30, mx1 = -(1 << 30), mn2 = 1 << 30, mx2 = -(1 << 30);
+        for (int om : W.members) {
+            const int k1 = om / N - h, k2 = om % N - h;
+            const int a1 = M[0] * k1 + M[1] * k2, a2 = M[2] * k1 + M[3] * k2;
+            mn1 = std::min(mn1, a1);
+            mx1 = std::max(mx1, a1);
+            mn2 = std::min(mn2, a2);
+            mx2 = std::max(mx2, a2);
+        }
+        const long long area = (long long)(mx1 - mn1 + 1) * (mx2 - mn2 + 1);
+        if (best < 0 || area < best) {
+            best = area;
+            std::memcpy(W.M, M, sizeof(W.M));
+            W.B[0] = mx1 - mn1 + 1;
+            W.B[1] = mx2 - mn2 + 1;
+            W.xc[0] = mn1 + W.B[0] / 2;
+            W.xc[1] = mn2 + W.B[1] / 2;
+        }
+    }
+    W.lo[0] = -(W.B[0] / 2);
+    W.lo[1] = -(W.B[1] / 2);
+    // M has determinant 1: inverse [[d, -b], [-c, a]]
+    W.Minv[0] = W.M[3];
+    W.Minv[1] = -W.M[1];
+    W.Minv[2] = -W.M[2];
+    W.Minv[3] = W.M[0];
+}
+
+// ---------------------------------------------------------------------------
+// NUFFT kernel: width and shape from the tolerance, Fourier transform by
+// Gauss-Legendre quadrature.
+// ---------------------------------------------------------------------------
+void es_parameters(double eps, double sigma, int forced_w, int &w, double &beta) {
+    if (forced_w > 0) {
+        w = forced_w;
+    } else {
+        w = (int)std::ceil(std::log(1.0 / eps) / (M_PI * std::sqrt(1.0 - 1.0 / sigma)));
+        w = std::max(w, 4);
+    }
+    // round up to a compiled width
+    int wc = 16;
+    for (int v : kInterpWidths)
+        if (v >= w) {
+            wc = v;
+            break;
+        }
+    w = std::min(wc, 16);
+    beta = 0.97 * M_PI * (1.0 - 0.5 / sigma) * w;
+}
+
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &wt) {
+    x.resize(n);
+    wt.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16)
+                break;
+        }
+        x[i] = z;
+        wt[i] = 2.0 / ((1 - z * z) * dp * dp);
+    }
+}
+
+// phi_hat(omega) = int_{-w/2}^{w/2} phi(z) exp(-2 pi i omega z) dz (phi even).
+double es_fourier(int w, double beta, double omega) {
+    static thread_local std::vector<double> gx, gw;
+    if (gx.empty())
+        gauss_legendre(200, gx, gw);
+    const double half = 0.5 * w;
+    double s = 0;
+    for (size_t i = 0; i < gx.size(); ++i) {
+        const double z = half * gx[i];
+        s += gw[i] * es_kernel<double>(z, 2.0 / w, beta) * std::cos(kTwoPi * omega * z);
+    }
+    return s * half;
+}
+
+// ---------------------------------------------------------------------------
+// Separation kernels (FP64).
+// ---------------------------------------------------------------------------
+__global__ void k_xcoef(Phase ph, int N, double2 *out) {
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (long long)N * N)
+        return;
+    const int n1 = (int)(p / N), n2 = (int)(p % N);
+    XCoef c = phase_xcoef(ph, (double)n1 / N, (double)n2 / N);
+    out[p] = make_double2(c.a, c.b);
+}
+
+__device__ inline double2 residual_entry(const Phase &ph, double2 xc, double e1, double e2, double k1, double k2) {
+    XCoef c{xc.x, xc.y};
+    double g1, g2;
+    phase_grad(ph, c, e1, e2, g1, g2);
+    const double r = residual_reduced(ph, c, g1, g2, k1, k2);
+    double cs, sn;
+    expi2pi(r, cs, sn);
+    return make_double2(cs, sn);
+}
+
+constexpr int kGramTile = 16;
+constexpr int kMaxSamples = 256;  // cap on r: the host eigen-solve is O(r^3)
+constexpr int kGramRows = 64;
+
+// Partial Gram G = A_C^H A_C over a row range, one 16 x 16 tile per block.
+__global__ __launch_bounds__(256) void k_gram(Phase ph, const double2 *__restrict__ xcoef, long long NN, double e1,
+                                              double e2, const double2 *__restrict__ cols, int r,
+                                              long long rows_per_block, double2 *__restrict__ partial) {
+    const int ti = blockIdx.y, tj = blockIdx.z;
+    if (ti > tj)
+        return;
+    __shared__ double2 Ai[kGramRows][kGramTile];
+    __shared__ double2 Aj[kGramRows][kGramTile];
+    const int tid = threadIdx.x;
+    const int ii = tid / kGramTile, jj = tid % kGramTile;
+    const int gi = ti * kGramTile + ii, gj = tj * kGramTile + jj;
+    const long long x0 = (long long)blockIdx.x * rows_per_block;
+    const long long x1 = (x0 + rows_per_block < NN) ? x0 + rows_per_block : NN;
+    double sr = 0, si = 0;
+    for (long long xb = x0; xb < x1; xb += kGramRows) {
+        for (int e = tid; e < 2 * kGramRows * kGramTile; e += blockDim.x) {
+            const int which = e / (kGramRows * kGramTile);
+            const int rr = (e % (kGramRows * kGramTile)) / kGramTile;
+            const int cc = e % kGramTile;
+            const long long x = xb + rr;
+            const int col = (which ? tj : ti) * kGramTile + cc;
+            double2 v = make_double2(0, 0);
+            if (x < x1 && col < r)
+                v = residual_entry(ph, xcoef[x], e1, e2, cols[col].x, cols[col].y);
+            if (which)
+                Aj[rr][cc] = v;
+            else
+                Ai[rr][cc] = v;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int rr = 0; rr < kGramRows; ++rr) {
+            const double2 a = Ai[rr][ii], b = Aj[rr][jj];
+            // conj(a) * b
+            sr += a.x * b.x + a.y * b.y;
+            si += a.x * b.y - a.y * b.x;
+        }
+        __syncthreads();
+    }
+    if (gi < r && gj < r)
+        partial[((long long)blockIdx.x * r + gi) * r + gj] = make_double2(sr, si);
+}
+
+__global__ void k_gram_reduce(const double2 *__restrict__ partial, int nblk, int r, double2 *__restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= r * r)
+        return;
+    const int i = e / r, j = e % r;
+    if (i > j)
+        return;
+    double sr = 0, si = 0;
+    for (int b = 0; b < nblk; ++b) {
+        const double2 v = partial[(long long)b * r * r + e];
+        sr += v.x;
+        si += v.y;
+    }
+    out[e] = make_double2(sr, si);
+}
+
+// gamma^x(x, t) = sum_c A(x, C_c) Z(c, t) for every grid point, stored as T (stride qpad).
+template <typename T>
+__global__ void k_gamma_x(Phase ph, const double2 *__restrict__ xcoef, long long NN, double e1, double e2,
+                          const double2 *__restrict__ cols, int r, const double2 *__restrict__ Z, int q, int qpad,
+                          cplx<T> *__restrict__ out) {
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= NN)
+        return;
+    constexpr int kQ = 32;
+    double ar[kQ], ai[kQ];
+    for (int t0 = 0; t0 < q; t0 += kQ) {
+        const int nt = min(kQ, q - t0);
+#pragma unroll
+        for (int t = 0; t < kQ; ++t)
+            ar[t] = ai[t] = 0;
+        const double2 xc = xcoef[x];
+        for (int c = 0; c < r; ++c) {
+            const double2 a = residual_entry(ph, xc, e1, e2, cols[c].x, cols[c].y);
+            const double2 *zr = Z + (long long)c * q + t0;
+#pragma unroll
+            for (int t = 0; t < kQ; ++t)
+                if (t < nt) {
+                    const double2 z = zr[t];
+                    ar[t] += a.x * z.x - a.y * z.y;
+                    ai[t] += a.x * z.y + a.y * z.x;
+                }
+        }
+#pragma unroll
+        for (int t = 0; t < kQ; ++t)
+            if (t < nt)
+                out[x * qpad + t0 + t] = cmake<T>((T)ar[t], (T)ai[t]);
+    }
+    for (int t = q; t < qpad; ++t)
+        out[x * qpad + t] = cmake<T>(0, 0);
+}
+
+// gamma^xi(m, t) = scale(m) * sum_i P(t, i) A(R_i, xi_m) for every member, stride qpad.
+template <typename T>
+__global__ void k_gamma_xi(Phase ph, int N, const int *__restrict__ omega, const double *__restrict__ scale, int nmem,
+                           const double4 *__restrict__ rows, int r, const double2 *__restrict__ P, int q, int qpad,
+                           cplx<T> *__restrict__ out) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nmem)
+        return;
+    const int h = N / 2;
+    const int om = omega[m];
+    const double k1 = om / N - h, k2 = om % N - h;
+    constexpr int kQ = 32;
+    double ar[kQ], ai[kQ];
+    for (int t0 = 0; t0 < q; t0 += kQ) {
+        const int nt = min(kQ, q - t0);
+#pragma unroll
+        for (int t = 0; t < kQ; ++t)
+            ar[t] = ai[t] = 0;
+        for (int i = 0; i < r; ++i) {
+            const double4 rw = rows[i];  // a, b, g1, g2 of row R_i
+            XCoef c{rw.x, rw.y};
+            const double ph_r = residual_reduced(ph, c, rw.z, rw.w, k1, k2);
+            double cs, sn;
+            expi2pi(ph_r, cs, sn);
+#pragma unroll
+            for (int t = 0; t < kQ; ++t)
+                if (t < nt) {
+                    const double2 pv = P[(long long)(t0 + t) * r + i];
+                    ar[t] += pv.x * cs - pv.y * sn;
+                    ai[t] += pv.x * sn + pv.y * cs;
+                }
+        }
+        const double s = scale[m];
+#pragma unroll
+        for (int t = 0; t < kQ; ++t)
+            if (t < nt)
+                out[(long long)m * qpad + t0 + t] = cmake<T>((T)(s * ar[t]), (T)(s * ai[t]));
+    }
+    for (int t = q; t < qpad; ++t)
+        out[(long long)m * qpad + t] = cmake<T>(0, 0);
+}
+
+__global__ void k_warp(Phase ph, int N, double e1, double e2, const long long *__restrict__ xidx, int nx,
+                       double *__restrict__ y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nx)
+        return;
+    const long long p = xidx[i];
+    const int n1 = (int)(p / N), n2 = (int)(p % N);
+    const double x1 = (double)n1 / N, x2 = (double)n2 / N;
+    const XCoef c = phase_xcoef(ph, x1, x2);
+    double g1, g2;
+    phase_grad(ph, c, e1, e2, g1, g2);
+    y[2 * i] = x1 + g1;
+    y[2 * i + 1] = x2 + g2;
+}
+
+template __global__ void k_gamma_x<float>(Phase, const double2 *, long long, double, double, const double2 *, int,
+                                          const double2 *, int, int, cplx<float> *);
+template __global__ void k_gamma_x<double>(Phase, const double2 *, long long, double, double, const double2 *, int,
+                                           const double2 *, int, int, cplx<double> *);
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+// Host FP64 residual entry exp(2 pi i Phi_ell(x, xi)) for flat grid index p.
+zd host_residual(const Phase &ph, int N, long long p, double e1, double e2, double k1, double k2) {
+    const double x1 = (double)(p / N) / N, x2 = (double)(p % N) / N;
+    XCoef c = phase_xcoef(ph, x1, x2);
+    double g1, g2;
+    phase_grad(ph, c, e1, e2, g1, g2);
+    const double r = residual_reduced(ph, c, g1, g2, k1, k2);
+    return zd(std::cos(kTwoPi * r), std::sin(kTwoPi * r));
+}
+
+// k distinct values in [0, n) from the splitmix64 stream `state`.
+template <typename I>
+static std::vector<I> sample_distinct(I n, int k, uint64_t &state) {
+    std::vector<I> out;
+    if ((long long)k >= (long long)n) {
+        out.resize((size_t)n);
+        for (I i = 0; i < n; ++i)
+            out[(size_t)i] = i;
+        return out;
+    }
+    std::map<I, I> swaps;  // sparse Fisher-Yates
+    for (int i = 0; i < k; ++i) {
+        state = splitmix64(state);
+        const I j = (I)(i + (long long)(state % (uint64_t)(n - i)));
+        auto get = [&](I v) {
+            auto it = swaps.find(v);
+            return it == swaps.end() ? v : it->second;
+        };
+        const I vi = get((I)i), vj = get(j);
+        swaps[j] = vi;
+        swaps[(I)i] = vj;
+        out.push_back(vj);
+    }
+    std::sort(out.begin(), out.end());
+    return out;
+}
+
+template std::vector<int> sample_distinct<int>(int, int, uint64_t &);
+template std::vector<long long> sample_distinct<long long>(long long, int, uint64_t &);
+
+// Randomized separation of one wedge (Section 3.3) with verification.
+fio_status separate_wedge(fio_plan_s *P, int l, const double2 *d_xcoef, DeviceScratch &scr) {
+    WedgeHost &W = P->wedges[l];
+    const int N = P->N;
+    const long long NN = (long long)N * N;
+    const int nmem = (int)W.members.size();
+    const double e1 = std::cos(W.theta), e2 = std::sin(W.theta);
+    const int h = N / 2;
+    double thr = P->tol * P->opt.sep_tol_frac;
+    const double target = 0.5 * P->tol;
+    int r = std::max(4, P->opt.r0);
+    const int rmax = std::max(r, kMaxSamples);
+    const int sv = std::max(8, P->opt.verify_samples);
+    uint64_t state = splitmix64(P->opt.seed ^ (0x51ED2701ull * (uint64_t)(l + 1)));
+    for (int attempt = 0; attempt < 10; ++attempt) {
+        W.attempts = attempt + 1;
+        const int rc = std::min(r, nmem);
+        W.C = sample_distinct<int>(nmem, rc, state);
+        std::vector<double2> cols(rc);
+        for (int c = 0; c < rc; ++c) {
+            const int om = W.members[W.C[c]];
+            cols[c] = make_double2(om / N - h, om % N - h);
+        }
+        // --- Gram of A_[C] on the GPU
+        FIO_HIP_TRY(scr.ensure_cols(rc));
+        FIO_HIP_TRY(hipMemcpy(scr.cols, cols.data(), rc * sizeof(double2), hipMemcpyHostToDevice));
+        const int nt = (rc + kGramTile - 1) / kGramTile;
+        const int nblk = (int)std::min<long long>(256, (NN + 4095) / 4096);
+        const long long rpb = (NN + nblk - 1) / nblk;
+        FIO_HIP_TRY(scr.ensure_partial((size_t)nblk * rc * rc, (size_t)rc * rc));
+        k_gram<<<dim3(nblk, nt, nt), 256>>>(P->phase, d_xcoef, NN, e1, e2, scr.cols, rc, rpb, scr.partial);
+        FIO_HIP_TRY(hipGetLastError());
+        k_gram_reduce<<<(rc * rc + 255) / 256, 256>>>(scr.partial, nblk, rc, scr.gram);
+        FIO_HIP_TRY(hipGetLastError());
+        std::vector<double2> g(rc * rc);
+        FIO_HIP_TRY(hipMemcpy(g.data(), scr.gram, rc * rc * sizeof(double2), hipMemcpyDeviceToHost));
+        std::vector<zd> G((size_t)rc * rc);
+        for (int i = 0; i < rc; ++i)
+            for (int j = i; j < rc; ++j) {
+                G[(size_t)i * rc + j] = zd(g[i * rc + j].x, g[i * rc + j].y);
+                G[(size_t)j * rc + i] = std::conj(G[(size_t)i * rc + j]);
+            }
+        std::vector<double> lam;
+        std::vector<zd> V;
+        eigh_jacobi(rc, G, lam, V);
+        const double s1 = std::sqrt(std::max(lam[0], 0.0));
+        int q = 0;
+        while (q < rc && std::sqrt(std::max(lam[q], 0.0)) > thr * s1)
+            ++q;
+        q = std::max(q, 1);
+        if (3 * q > rc && rc < nmem && r < rmax) {
+            r = std::min(2 * r, rmax);
+            continue;
+        }
+        // Z = V_q S_q^-1
+        W.Z.assign((size_t)rc * q, zd(0, 0));
+        for (int c = 0; c < rc; ++c)
+            for (int t = 0; t < q; ++t)
+                W.Z[(size_t)c * q + t] = V[(size_t)c * rc + t] / std::sqrt(lam[t]);
+        // rows R, U_R = A_RC Z, P = pinv(U_R)
+        const int rr = (int)std::min<long long>(std::max(rc, 2 * q), NN);
+        W.R = sample_distinct<long long>(NN, rr, state);
+        std::vector<zd> UR((size_t)rr * q, zd(0, 0));
+        for (int i = 0; i < rr; ++i)
+            for (int c = 0; c < rc; ++c) {
+                const zd a = host_residual(P->phase, N, W.R[i], e1, e2, cols[c].x, cols[c].y);
+                for (int t = 0; t < q; ++t)
+                    UR[(size_t)i * q + t] += a * W.Z[(size_t)c * q + t];
+            }
+        pinv_tall(rr, q, UR, W.P, 1e-7);
+        W.q = q;
+        W.r = rc;
+        // --- s x s estimate (Section 4)
+        const int sg = (int)std::min<long long>(sv, NN), sd = std::min(sv, nmem);
+        std::vector<long long> Gam = sample_distinct<long long>(NN, sg, state);
+        std::vector<int> Del = sample_distinct<int>(nmem, sd, state);
+        std::vector<zd> UG((size_t)sg * q, zd(0, 0)), TD((size_t)q * sd, zd(0, 0));
+        for (int i = 0; i < sg; ++i)
+            for (int c = 0; c < rc; ++c) {
+                const zd a = host_residual(P->phase, N, Gam[i], e1, e2, cols[c].x, cols[c].y);
+                for (int t = 0; t < q; ++t)
+                    UG[(size_t)i * q + t] += a * W.Z[(size_t)c * q + t];
+            }
+        for (int j = 0; j < sd; ++j) {
+            const int om = W.members[Del[j]];
+            const double k1 = om / N - h, k2 = om % N - h;
+            for (int i = 0; i < rr; ++i) {
+                const zd a = host_residual(P->phase, N, W.R[i], e1, e2, k1, k2);
+                for (int t = 0; t < q; ++t)
+                    TD[(size_t)t * sd + j] += W.P[(size_t)t * rr + i] * a;
+            }
+        }
+        double num = 0, den = 0;
+        for (int i = 0; i < sg; ++i)
+            for (int j = 0; j < sd; ++j) {
+                const int om = W.members[Del[j]];
+                const zd a = host_residual(P->phase, N, Gam[i], e1, e2, om / N - h, om % N - h);
+                zd s(0, 0);
+                for (int t = 0; t < q; ++t)
+                    s += UG[(size_t)i * q + t] * TD[(size_t)t * sd + j];
+                num += std::norm(a - s);
+                den += std::norm(a);
+            }
+        W.sep_err = std::sqrt(num / std::max(den, 1e-300));
+        if (W.sep_err <= target || attempt == 9)
+            return FIO_OK;
+        // the estimate missed the target: tighten the threshold and, while
+        // columns remain unsampled, sample more of them
+        thr *= 0.5;
+        if (rc < nmem && r < rmax)
+            r = std::min(2 * r, rmax);
+    }
+    return FIO_OK;
+}
+
+hipError_t DeviceScratch::ensure_cols(int n) {
+    if (n <= ncols)
+        return hipSuccess;
+    if (cols)
+        (void)hipFree(cols);
+    ncols = n;
+    return hipMalloc(&cols, (size_t)n * sizeof(double2));
+}
+hipError_t DeviceScratch::ensure_partial(size_t npart, size_t ngram) {
+    if (npart > npartial) {
+        if (partial)
+            (void)hipFree(partial);
+        npartial = npart;
+        hipError_t e = hipMalloc(&partial, npart * sizeof(double2));
+        if (e != hipSuccess)
+            return e;
+    }
+    if (ngram > ngram_) {
+        if (gram)
+            (void)hipFree(gram);
+        ngram_ = ngram;
+        return hipMalloc(&gram, ngram * sizeof(double2));
+    }
+    return hipSuccess;
+}
+DeviceScratch::~DeviceScratch() {
+    if (cols)
+        (void)hipFree(cols);
+    if (partial)
+        (void)hipFree(partial);
+    if (gram)
+        (void)hipFree(gram);
+}
+
+// ---------------------------------------------------------------------------
+// Device storage of factors, tables and workspace
+// ---------------------------------------------------------------------------
+template <typename T>
+static fio_status store_factors(fio_plan_s *P, const double2 *d_xcoef) {
+    const int N = P->N;
+    const long long NN = (long long)N * N;
+    const int h = N / 2;
+    double2 *d_cols = nullptr, *d_mat = nullptr;
+    double4 *d_rows = nullptr;
+    double *d_scale = nullptr;
+    struct Guard {
+        std::vector<void *> p;
+        ~Guard() {
+            for (void *v : p)
+                if (v)
+                    (void)hipFree(v);
+        }
+    } guard;
+    size_t maxr = 1, maxm = 1, maxz = 1;
+    for (const WedgeHost &W : P->wedges) {
+        maxr = std::max(maxr, std::max(W.C.size(), W.R.size()));
+        maxm = std::max(maxm, W.members.size());
+        maxz = std::max(maxz, std::max(W.Z.size(), W.P.size()));
+    }
+    FIO_HIP_TRY(hipMalloc(&d_cols, maxr * sizeof(double2)));
+    guard.p.push_back(d_cols);
+    FIO_HIP_TRY(hipMalloc(&d_rows, maxr * sizeof(double4)));
+    guard.p.push_back(d_rows);
+    FIO_HIP_TRY(hipMalloc(&d_mat, maxz * sizeof(double2)));
+    guard.p.push_back(d_mat);
+    FIO_HIP_TRY(hipMalloc(&d_scale, maxm * sizeof(double)));
+    guard.p.push_back(d_scale);
+    cplx<T> *gx = static_cast<cplx<T> *>(P->d_gx);
+    cplx<T> *gxi = static_cast<cplx<T> *>(P->d_gxi);
+    for (int l = 0; l < P->L; ++l) {
+        WedgeHost &W = P->wedges[l];
+        const WedgeDev &D = P->wdev[l];
+        if (W.q == 0)
+            continue;
+        const double e1 = std::cos(W.theta), e2 = std::sin(W.theta);
+        const int rc = (int)W.C.size(), rr = (int)W.R.size();
+        // gamma^x
+        std::vector<double2> cols(rc);
+        for (int c = 0; c < rc; ++c) {
+            const int om = W.members[W.C[c]];
+            cols[c] = make_double2(om / N - h, om % N - h);
+        }
+        FIO_HIP_TRY(hipMemcpy(d_cols, cols.data(), rc * sizeof(double2), hipMemcpyHostToDevice));
+        FIO_HIP_TRY(hipMemcpy(d_mat, W.Z.data(), W.Z.size() * sizeof(double2), hipMemcpyHostToDevice));
+        k_gamma_x<T><<<(unsigned)((NN + 255) / 256), 256>>>(P->phase, d_xcoef, NN, e1, e2, d_cols, rc, d_mat, W.q,
+                                                            W.qpad, gx + D.gx_off);
+        FIO_HIP_TRY(hipGetLastError());
+        // gamma^xi with deconvolution and 1/N
+        std::vector<double4> rows(rr);
+        for (int i = 0; i < rr; ++i) {
+            const long long p = W.R[i];
+            const double x1 = (double)(p / N) / N, x2 = (double)(p % N) / N;
+            XCoef c = phase_xcoef(P->phase, x1, x2);
+            double g1, g2;
+            phase_grad(P->phase, c, e1, e2, g1, g2);
+            rows[i] = make_double4(c.a, c.b, g1, g2);
+        }
+        std::vector<double> scale(W.members.size());
+        for (size_t m = 0; m < W.members.size(); ++m) {
+            const int om = W.members[m];
+            const int k1 = om / N - h, k2 = om % N - h;
+            const int a1 = W.M[0] * k1 + W.M[1] * k2 - W.xc[0], a2 = W.M[2] * k1 + W.M[3] * k2 - W.xc[1];
+            scale[m] = W.dec1[a1 - W.lo[0]] * W.dec2[a2 - W.lo[1]] / N;
+        }
+        FIO_HIP_TRY(hipMemcpy(d_rows, rows.data(), rr * sizeof(double4), hipMemcpyHostToDevice));
+        FIO_HIP_TRY(hipMemcpy(d_mat, W.P.data(), W.P.size() * sizeof(double2), hipMemcpyHostToDevice));
+        FIO_HIP_TRY(hipMemcpy(d_scale, scale.data(), scale.size() * sizeof(double), hipMemcpyHostToDevice));
+        const int nmem = (int)W.members.size();
+        k_gamma_xi<T><<<(nmem + 255) / 256, 256>>>(P->phase, N, P->d_omega + D.mem_off, d_scale, nmem, d_rows, rr,
+                                                   d_mat, W.q, W.qpad, gxi + D.gxi_off);
+        FIO_HIP_TRY(hipGetLastError());
+        FIO_HIP_TRY(hipDeviceSynchronize());
+    }
+    return FIO_OK;
+}
+
+fio_status build_plan(fio_plan_s *P) {
+    using clock = std::chrono::steady_clock;
+    const auto t_start = clock::now();
+    const int N = P->N;
+    const long long NN = (long long)N * N;
+    const int h = N / 2;
+    FIO_HIP_TRY(hipGetDevice(&P->device));
+    // 1. partition
+    std::vector<double> thetas;
+    if (P->opt.partition == FIO_PART_CORONAE) {
+        partition_coronae(N, P->wedge_of, thetas);
+    } else {
+        int L = P->opt.n_wedges;
+        if (L <= 0)
+            L = 8 * (int)std::ceil(std::sqrt((double)N) / 8.0);
+        partition_equiangular(N, L, P->wedge_of, thetas);
+    }
+    P->L = (int)thetas.size();
+    P->wedges.assign(P->L, WedgeHost());
+    for (int l = 0; l < P->L; ++l)
+        P->wedges[l].theta = thetas[l];
+    for (long long i = 0; i < NN; ++i)
+        P->wedges[P->wedge_of[i]].members.push_back((int)i);
+    // 2. NUFFT parameters and geometry
+    P->sigma = P->opt.sigma > 0 ? P->opt.sigma : 2.0;
+    es_parameters(P->tol * P->opt.nufft_tol_frac, P->sigma, P->opt.kernel_width, P->w, P->beta);
+    std::map<int, int> fft_index;
+    auto fft_for = [&](int n) -> int {
+        auto it = fft_index.find(n);
+        if (it != fft_index.end())
+            return it->second;
+        FftPlan pl;
+        fft_make_plan(n, pl);
+        const int id = (int)P->fftplans.size();
+        P->fftplans.push_back(pl);
+        P->fft_len.push_back(n);
+        P->tw_off.push_back((int)P->tw_total);
+        P->tw_total += n;
+        fft_index[n] = id;
+        return id;
+    };
+    for (WedgeHost &W : P->wedges) {
+        if (W.members.empty())
+            continue;
+        wedge_geometry(N, W);
+        for (int d = 0; d < 2; ++d) {
+            W.n[d] = fft_nice_size(std::max((int)std::ceil(P->sigma * W.B[d]), 2 * P->w));
+        }
+        W.dec1.resize(W.B[0]);
+        W.dec2.resize(W.B[1]);
+        for (int i = 0; i < W.B[0]; ++i)
+            W.dec1[i] = 1.0 / es_fourier(P->w, P->beta, (double)(W.lo[0] + i) / W.n[0]);
+        for (int i = 0; i < W.B[1]; ++i)
+            W.dec2[i] = 1.0 / es_fourier(P->w, P->beta, (double)(W.lo[1] + i) / W.n[1]);
+    }
+    // 3. randomized separation
+    double2 *d_xcoef = nullptr;
+    FIO_HIP_TRY(hipMalloc(&d_xcoef, NN * sizeof(double2)));
+    struct XGuard {
+        double2 *p;
+        ~XGuard() {
+            if (p)
+                (void)hipFree(p);
+        }
+    } xg{d_xcoef};
+    k_xcoef<<<(unsigned)((NN + 255) / 256), 256>>>(P->phase, N, d_xcoef);
+    FIO_HIP_TRY(hipGetLastError());
+    {
+        DeviceScratch scr;
+        for (int l = 0; l < P->L; ++l) {
+            if (P->wedges[l].members.empty())
+                continue;
+            fio_status st = separate_wedge(P, l, d_xcoef, scr);
+            if (st != FIO_OK)
+                return st;
+        }
+    }
+    // 4. layout
+    P->esize = P->precision == FIO_F64 ? 16 : 8;
+    const long long cap = kMaxLdsBytes / (2 * (long long)P->esize);  // complex elements per FFT buffer
+    P->qmax = 0;
+    P->wdev.assign(P->L, WedgeDev());
+    long long map_off = 0, mem_off = 0, gxi_off = 0, gx_off = 0, H_off = 0, G_off = 0;
+    P->row_first.assign(P->L + 1, 0);
+    P->col_first.assign(P->L + 1, 0);
+    size_t lds_rows = 0, lds_cols = 0;
+    for (int l = 0; l < P->L; ++l) {
+        WedgeHost &W = P->wedges[l];
+        WedgeDev &D = P->wdev[l];
+        std::memset(&D, 0, sizeof(D));
+        D.e1 = std::cos(W.theta);
+        D.e2 = std::sin(W.theta);
+        P->row_first[l] = (int)P->rows.size();
+        P->col_first[l] = (int)P->cols.size();
+        if (W.members.empty() || W.q == 0)
+            continue;
+        W.qpad = W.q + (W.q & 1);
+        P->qmax = std::max(P->qmax, W.qpad);
+        // y' = M^{-T} y ; psi = y . M^{-1} xi_c
+        D.mt[0] = W.Minv[0];
+        D.mt[1] = W.Minv[2];
+        D.mt[2] = W.Minv[1];
+        D.mt[3] = W.Minv[3];
+        D.cvec[0] = W.Minv[0] * W.xc[0] + W.Minv[1] * W.xc[1];
+        D.cvec[1] = W.Minv[2] * W.xc[0] + W.Minv[3] * W.xc[1];
+        D.n1 = W.n[0];
+        D.n2 = W.n[1];
+        D.B1 = W.B[0];
+        D.B2 = W.B[1];
+        D.lo1 = W.lo[0];
+        D.lo2 = W.lo[1];
+        D.q = W.qpad;
+        D.nmem = (int)W.members.size();
+        D.fft1 = fft_for(W.n[0]);
+        D.fft2 = fft_for(W.n[1]);
+        D.tw1 = P->tw_off[D.fft1];
+        D.tw2 = P->tw_off[D.fft2];
+        if (W.n[0] > cap || W.n[1] > cap)
+            return (set_error("oversampled grid too long for the LDS transform"), FIO_ENOTSUP);
+        D.map_off = map_off;
+        map_off += (long long)W.B[0] * W.B[1];
+        D.mem_off = mem_off;
+        mem_off += W.members.size();
+        D.gxi_off = gxi_off;
+        gxi_off += (long long)W.members.size() * W.qpad;
+        D.gx_off = gx_off;
+        gx_off += NN * W.qpad;
+        D.H_off = H_off;
+        H_off += (long long)W.B[0] * W.n[1] * W.qpad;
+        D.G_off = G_off;
+        G_off += (long long)W.n[0] * W.n[1] * W.qpad;
+        // stage-1 items: box rows, rank chunks fitting the LDS
+        const int tn = (int)std::max<long long>(1, std::min<long long>(W.qpad, cap / W.n[1]));
+        for (int k1 = 0; k1 < W.B[0]; ++k1)
+            for (int t0 = 0; t0 < W.qpad; t0 += tn)
+                P->rows.push_back(RowItem{l, k1, t0, std::min(tn, W.qpad - t0)});
+        lds_rows = std::max(lds_rows, (size_t)2 * W.n[1] * tn * P->esize);
+        // stage-2 items: chunks of adjacent transforms tau = j2 * q + t
+        const long long ntau = (long long)W.n[1] * W.qpad;
+        const int nb = (int)std::max<long long>(1, std::min<long long>(ntau, cap / W.n[0]));
+        for (long long t0 = 0; t0 < ntau; t0 += nb)
+            P->cols.push_back(ColItem{l, (int)t0, (int)std::min<long long>(nb, ntau - t0), 0});
+        lds_cols = std::max(lds_cols, (size_t)2 * W.n[0] * nb * P->esize);
+    }
+    P->row_first[P->L] = (int)P->rows.size();
+    P->col_first[P->L] = (int)P->cols.size();
+    P->lds_rows = lds_rows;
+    P->lds_cols = lds_cols;
+    P->map_total = map_off;
+    P->mem_total = mem_off;
+    P->gxi_total = gxi_off;
+    P->gx_total = gx_off;
+    P->H_total = H_off;
+    P->G_total = G_off;
+    if (P->qmax == 0)
+        return (set_error("no wedge has a nonzero rank"), FIO_EINVAL);
+    // 5. device tables
+    std::vector<int> map(std::max<long long>(1, map_off), -1), omega(std::max<long long>(1, mem_off));
+    for (int l = 0; l < P->L; ++l) {
+        WedgeHost &W = P->wedges[l];
+        const WedgeDev &D = P->wdev[l];
+        if (W.members.empty() || W.q == 0)
+            continue;
+        for (size_t m = 0; m < W.members.size(); ++m) {
+            const int om = W.members[m];
+            const int k1 = om / N - h, k2 = om % N - h;
+            const int a1 = W.M[0] * k1 + W.M[1] * k2 - W.xc[0] - W.lo[0];
+            const int a2 = W.M[2] * k1 + W.M[3] * k2 - W.xc[1] - W.lo[1];
+            map[D.map_off + (long long)a1 * W.B[1] + a2] = (int)m;
+            omega[D.mem_off + m] = om;
+        }
+    }
+    const size_t es = P->esize;
+    FIO_HIP_TRY(hipMalloc(&P->d_wedges, sizeof(WedgeDev) * P->L));
+    FIO_HIP_TRY(hipMemcpy(P->d_wedges, P->wdev.data(), sizeof(WedgeDev) * P->L, hipMemcpyHostToDevice));
+    FIO_HIP_TRY(hipMalloc(&P->d_fftplans, sizeof(FftPlan) * P->fftplans.size()));
+    FIO_HIP_TRY(hipMemcpy(P->d_fftplans, P->fftplans.data(), sizeof(FftPlan) * P->fftplans.size(),
+                          hipMemcpyHostToDevice));
+    FIO_HIP_TRY(hipMalloc(&P->d_rows, sizeof(RowItem) * std::max<size_t>(1, P->rows.size())));
+    FIO_HIP_TRY(hipMemcpy(P->d_rows, P->rows.data(), sizeof(RowItem) * P->rows.size(), hipMemcpyHostToDevice));
+    FIO_HIP_TRY(hipMalloc(&P->d_cols, sizeof(ColItem) * std::max<size_t>(1, P->cols.size())));
+    FIO_HIP_TRY(hipMemcpy(P->d_cols, P->cols.data(), sizeof(ColItem) * P->cols.size(), hipMemcpyHostToDevice));
+    FIO_HIP_TRY(hipMalloc(&P->d_map, sizeof(int) * map.size()));
+    FIO_HIP_TRY(hipMemcpy(P->d_map, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice));
+    FIO_HIP_TRY(hipMalloc(&P->d_omega, sizeof(int) * omega.size()));
+    FIO_HIP_TRY(hipMemcpy(P->d_omega, omega.data(), sizeof(int) * omega.size(), hipMemcpyHostToDevice));
+    // twiddles exp(+2 pi i m / n) in FP64, stored in the plan precision
+    {
+        std::vector<double> tw(2 * P->tw_total);
+        for (size_t f = 0; f < P->fftplans.size(); ++f) {
+            const int n = P->fft_len[f];
+            for (int m = 0; m < n; ++m) {
+                tw[2 * (P->tw_off[f] + m)] = std::cos(kTwoPi * m / n);
+                tw[2 * (P->tw_off[f] + m) + 1] = std::sin(kTwoPi * m / n);
+            }
+        }
+        FIO_HIP_TRY(hipMalloc(&P->d_tw, es * P->tw_total));
+        if (P->precision == FIO_F64) {
+            FIO_HIP_TRY(hipMemcpy(P->d_tw, tw.data(), es * P->tw_total, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> twf(tw.begin(), tw.end());
+            FIO_HIP_TRY(hipMemcpy(P->d_tw, twf.data(), es * P->tw_total, hipMemcpyHostToDevice));
+        }
+    }
+    FIO_HIP_TRY(hipMalloc(&P->d_gxi, es * std::max<long long>(1, gxi_off)));
+    FIO_HIP_TRY(hipMalloc(&P->d_gx, es * std::max<long long>(1, gx_off)));
+    P->factor_bytes = (long long)es * (gxi_off + gx_off);
+    // workspace: bchunk right-hand sides
+    P->bchunk = std::max(1, P->opt.max_batch);
+    const long long per_rhs = (long long)es * (H_off + G_off);
+    const long long budget = 24LL << 30;
+    while (P->bchunk > 1 && per_rhs * P->bchunk > budget)
+        P->bchunk /= 2;
+    FIO_HIP_TRY(hipMalloc(&P->d_H, es * std::max<long long>(1, H_off) * P->bchunk));
+    FIO_HIP_TRY(hipMalloc(&P->d_G, es * std::max<long long>(1, G_off) * P->bchunk));
+    P->workspace_bytes = per_rhs * P->bchunk;
+    // 6. factors
+    fio_status st = P->precision == FIO_F64 ? store_factors<double>(P, d_xcoef) : store_factors<float>(P, d_xcoef);
+    if (st != FIO_OK)
+        return st;
+    FIO_HIP_TRY(apply_prepare(P));
+    FIO_HIP_TRY(hipDeviceSynchronize());
+    P->plan_ms = std::chrono::duration<double, std::milli>(clock::now() - t_start).count();
+    return FIO_OK;
+}
+
+}  // namespace fio

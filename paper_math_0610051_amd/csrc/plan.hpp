@@ -1,0 +1,123 @@
+// Internal plan structures of the FIO library (host side and the POD
+// descriptors the kernels read).
+#pragma once
+
+#include <complex>
+#include <string>
+#include <vector>
+
+#include "../../include/fio.h"
+#include "common.hpp"
+#include "fft.hpp"
+
+namespace fio {
+
+using zd = std::complex<double>;
+
+// Device-visible descriptor of one wedge W_ell and its NUFFT box (Section 3.4).
+struct WedgeDev {
+    double e1, e2;       // centre direction xi_hat_ell
+    double mt[4];        // M^{-T} (row-major): y' = M^{-T} y
+    double cvec[2];      // M^{-1} xi_c: modulation phase psi(x) = y . M^{-1} xi_c
+    int n1, n2;          // oversampled grid
+    int B1, B2;          // sheared, centred box
+    int lo1, lo2;        // centred frequency of box index 0 (lo = -floor(B/2))
+    int q;               // stored rank (even, zero-padded factors)
+    int nmem;            // |W_ell|
+    int tw1, tw2;        // twiddle-table offsets for lengths n1, n2
+    int fft1, fft2;      // FFT plan indices for n1, n2
+    int pad0, pad1;
+    long long map_off;   // box map: int32 per box cell -> member index or -1
+    long long mem_off;   // member tables: centred Omega index per member
+    long long gxi_off;   // gamma^xi (deconvolved, 1/N folded in), nmem * q complex
+    long long gx_off;    // gamma^x, N^2 * q complex
+    long long H_off;     // per-RHS row-transformed box, B1 * n2 * q complex
+    long long G_off;     // per-RHS oversampled grid, n1 * n2 * q complex
+};
+
+// Work items of the two FFT stages.
+struct RowItem {   // stage 1: one box row k1 of wedge ell, ranks [t0, t0 + tn)
+    int l, k1, t0, tn;
+};
+struct ColItem {   // stage 2: transforms tau in [tau0, tau0 + nb) of wedge ell (tau = j2 * q + t)
+    int l, tau0, nb, pad;
+};
+
+// Kernel-side view of a plan (passed by value).
+template <typename T>
+struct PlanArgs {
+    Phase phase;
+    int N, L, w, qmax;
+    T beta, two_over_w;
+    const WedgeDev *wedges;
+    const FftPlan *fftplans;
+    const int *map;
+    const int *omega;
+    const cplx<T> *gxi;
+    const cplx<T> *gx;
+    const cplx<T> *tw;
+    cplx<T> *H;
+    cplx<T> *G;
+    long long H_stride, G_stride;  // per right-hand side
+};
+
+struct WedgeHost {
+    double theta = 0;
+    std::vector<int> members;   // centred Omega indices
+    int M[4] = {1, 0, 0, 1}, Minv[4] = {1, 0, 0, 1};
+    int xc[2] = {0, 0}, B[2] = {1, 1}, lo[2] = {0, 0}, n[2] = {2, 2};
+    int q = 0, qpad = 0, r = 0, attempts = 0;
+    double sep_err = 0;
+    std::vector<int> C;          // sampled member positions (columns)
+    std::vector<long long> R;    // sampled grid rows
+    std::vector<zd> Z;           // r x q, V S^-1 (row-major)
+    std::vector<zd> P;           // q x r, U_[R]^+ (row-major)
+    std::vector<double> dec1, dec2;  // 1 / phi_hat along each box axis
+};
+
+}  // namespace fio
+
+struct fio_plan_s {
+    int N = 0, L = 0, precision = FIO_F32, device = 0;
+    fio::Phase phase{};
+    double tol = 0;
+    fio_options opt{};
+    int w = 0;
+    double sigma = 2.0, beta = 0;
+    int qmax = 0;
+    int fallback = 0, factor_mode = FIO_FACTORS_STORED;
+    double plan_ms = 0;
+    std::vector<fio::WedgeHost> wedges;
+    std::vector<int> wedge_of;   // N*N, centred
+    std::vector<fio::WedgeDev> wdev;
+    std::vector<fio::RowItem> rows;
+    std::vector<fio::ColItem> cols;
+    std::vector<fio::FftPlan> fftplans;
+    std::vector<int> fft_len;    // length of each fft plan
+    std::vector<int> tw_off;     // twiddle offset per fft plan
+    long long tw_total = 0;
+    long long map_total = 0, mem_total = 0, gxi_total = 0, gx_total = 0, H_total = 0, G_total = 0;
+    int bchunk = 8;
+    size_t esize = 8;            // bytes of one complex element
+    size_t lds_rows = 0, lds_cols = 0;  // dynamic LDS of the two FFT stages
+    // device buffers
+    fio::WedgeDev *d_wedges = nullptr;
+    fio::FftPlan *d_fftplans = nullptr;
+    fio::RowItem *d_rows = nullptr;
+    fio::ColItem *d_cols = nullptr;
+    int *d_map = nullptr, *d_omega = nullptr;
+    void *d_gxi = nullptr, *d_gx = nullptr, *d_tw = nullptr, *d_H = nullptr, *d_G = nullptr;
+    long long factor_bytes = 0, workspace_bytes = 0;
+    // rows of the row/column work tables restricted to a wedge range are
+    // found by scanning: rows and cols are sorted by wedge.
+    std::vector<int> row_first, col_first;   // L+1 prefix offsets
+    // optional per-stage event timing
+    int profiling = 0;
+    struct StageEvents {
+        int stage;
+        hipEvent_t start, stop;
+    };
+    std::vector<StageEvents> prof_events;
+    double prof_ms[3] = {0, 0, 0};
+    long long prof_launches[3] = {0, 0, 0};
+};

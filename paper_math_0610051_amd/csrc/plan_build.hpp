@@ -1,0 +1,31 @@
+// Plan-construction internals shared by plan.hip and abi.hip.
+#pragma once
+
+#include <vector>
+
+#include "plan.hpp"
+
+namespace fio {
+
+// Device scratch reused across the wedges of one plan build.
+struct DeviceScratch {
+    double2 *cols = nullptr, *partial = nullptr, *gram = nullptr;
+    int ncols = 0;
+    size_t npartial = 0, ngram_ = 0;
+    hipError_t ensure_cols(int n);
+    hipError_t ensure_partial(size_t npart, size_t ngram);
+    ~DeviceScratch();
+};
+
+void partition_equiangular(int N, int L, std::vector<int> &ids, std::vector<double> &thetas);
+void partition_coronae(int N, std::vector<int> &ids, std::vector<double> &thetas);
+void wedge_geometry(int N, WedgeHost &W);
+void es_parameters(double eps, double sigma, int forced_w, int &w, double &beta);
+double es_fourier(int w, double beta, double omega);
+zd host_residual(const Phase &ph, int N, long long p, double e1, double e2, double k1, double k2);
+fio_status build_plan(fio_plan_s *P);
+
+__global__ void k_warp(Phase ph, int N, double e1, double e2, const long long *__restrict__ xidx, int nx,
+                       double *__restrict__ y);
+
+}  // namespace fio

@@ -1,0 +1,283 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Every check calls the library through its ctypes binding and compares with
+oracle/ on the same seeded inputs.  Integer work (the wedge partition) must
+agree bit for bit; floating-point results must meet the relative l2
+tolerance the plan was built for (default 1e-4), as the paper measures
+errors (Section 4).  Element-wise maxima are also bounded.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import fio_inputs as fi
+from oracle import direct as od
+from oracle import reference as ref
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    od.build(force=False)
+    from paper_math_0610051_amd import fio  # noqa: F401  (raises if the library is missing)
+
+
+def _plan(N, kind, params, tol, **kw):
+    from paper_math_0610051_amd import Plan
+    print("plan N=%d %s %s tol=%g %s" % (N, kind, params, tol, kw), flush=True)
+    return Plan(N, kind, tol, params=params, **kw)
+
+
+def _dev(a, precision="f32"):
+    dt = torch.complex128 if precision == "f64" else torch.complex64
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dt).cuda()
+
+
+def _apply(plan, fhat, precision="f32"):
+    u = plan.apply(_dev(fhat, precision))
+    torch.cuda.synchronize()
+    return u.cpu().numpy().astype(np.complex128)
+
+
+# ------------------------------------------------------------------ a2: partition (integer, bit-exact)
+@pytest.mark.parametrize("N,partition,L", [(64, "equiangular", 0), (256, "equiangular", 0), (100, "equiangular", 24),
+                                           (64, "coronae", 0), (256, "coronae", 0)])
+def test_wedge_map_bit_exact(N, partition, L):
+    p = _plan(N, "c1c2", (1.0,), 1e-2, partition=partition, n_wedges=L)
+    if partition == "coronae":
+        ids, th = ref.corona_partition(N)
+    else:
+        ids, th = ref.equiangular_partition(N, L or 8 * math.ceil(math.sqrt(N) / 8))
+    assert np.array_equal(p.wedge_map(), ids)
+    assert p.L == len(th)
+    for ell in range(p.L):
+        assert abs(p.wedge_info(ell)["theta"] - th[ell]) < 1e-15
+
+
+def test_wedge_boxes_hold_their_sheared_members():
+    N = 128
+    p = _plan(N, "c1c2", (1.0,), 1e-2)
+    ids = p.wedge_map().ravel()
+    k1, k2 = ref.grid_xi(N)
+    for ell in range(p.L):
+        w = p.wedge_info(ell)
+        M = np.array(w["M"]).reshape(2, 2)
+        assert round(np.linalg.det(M)) == 1
+        sel = ids == ell
+        a = M @ np.stack([k1[sel], k2[sel]]) - np.array(w["xi_c"])[:, None]
+        for d in range(2):
+            assert a[d].min() >= w["lo"][d] and a[d].max() < w["lo"][d] + w["box"][d]
+            assert w["fine"][d] >= 2 * w["box"][d]
+
+
+# ------------------------------------------------------------------ a3: warped points (FP64)
+@pytest.mark.parametrize("kind,params", [("c1c2", (1.3,)), ("radial", (0.05, 0.5)), ("paper_ellipse", (1.0,))])
+def test_warped_points_fp64(kind, params):
+    N = 256
+    p = _plan(N, kind, params, 1e-2)
+    rng = np.random.default_rng(1)
+    xs = fi.sample_points(N, 500, rng)
+    x1, x2 = ref.x_of_index(N, xs)
+    for ell in (0, 3, p.L - 1):
+        th = p.wedge_info(ell)["theta"]
+        y = p.wedge_warp(ell, xs)
+        e1, e2 = ref.warp(ref.KINDS[kind], params, x1, x2, th)
+        assert np.max(np.abs(y[:, 0] - e1)) < 1e-13 and np.max(np.abs(y[:, 1] - e2)) < 1e-13
+
+
+# ------------------------------------------------------------------ a4: separated factors vs exp(2 pi i Phi_ell)
+@pytest.mark.parametrize("precision,tol", [("f32", 1e-4), ("f64", 1e-6)])
+def test_stored_factors_reproduce_residual_kernel(precision, tol):
+    """Independent s x s estimate (Section 4) of the stored factors against the oracle's A."""
+    N = 128
+    p = _plan(N, "c1c2", (1.0,), tol, precision=precision)
+    ids = p.wedge_map().ravel()
+    k1, k2 = ref.grid_xi(N)
+    rng = np.random.default_rng(2)
+    for ell in range(0, p.L, 3):
+        th = p.wedge_info(ell)["theta"]
+        members = np.nonzero(ids == ell)[0]
+        G = fi.sample_points(N, 200, rng)
+        D = np.sort(rng.choice(members, size=min(200, members.size), replace=False))
+        gx, gxi = p.wedge_factors(ell, G, D)
+        A = ref.residual_matrix(N, 2, (1.0,), th, G, k1[D], k2[D])
+        err = np.linalg.norm(A - gx @ gxi.T) / np.linalg.norm(A)
+        assert err < tol, (ell, err)
+
+
+# ------------------------------------------------------------------ closed forms through the fast path
+@pytest.mark.parametrize("N", [64, 130])
+def test_identity_phase_returns_input(N):
+    """Phi = x.xi: u = f (rank 1, so only NUFFT and FP32 error remain)."""
+    rng = np.random.default_rng(3)
+    f = fi.complex_gaussian(N, rng)
+    p = _plan(N, "linear", (0.0, 0.0), 1e-4)
+    u = _apply(p, fi.fhat_from_f(f))
+    assert ref.rel_l2(u, f) < 1e-4
+    assert np.max(np.abs(u - f)) < 1e-4 * np.max(np.abs(f)) * 5
+
+
+def test_grid_shift_is_a_roll():
+    N = 96
+    rng = np.random.default_rng(4)
+    f = fi.complex_gaussian(N, rng)
+    p = _plan(N, "linear", (5 / N, -11 / N), 1e-4)
+    u = _apply(p, fi.fhat_from_f(f))
+    assert ref.rel_l2(u, np.roll(f, (-5, 11), axis=(0, 1))) < 1e-4
+
+
+@pytest.mark.parametrize("ct", [0.05, -0.12])
+def test_wave_multiplier_closed_form(ct):
+    N = 128
+    rng = np.random.default_rng(5)
+    f = fi.complex_gaussian(N, rng)
+    p = _plan(N, "wave", (ct,), 1e-4)
+    u = _apply(p, fi.fhat_from_f(f))
+    expect = ref.multiplier_solution(N, lambda a, b: ref.h(1, (ct,), 0.0, 0.0, a, b), f)
+    assert ref.rel_l2(u, expect) < 1e-4
+
+
+# ------------------------------------------------------------------ end to end vs the direct sum
+@pytest.mark.parametrize("N,kind,params,tol,precision", [
+    (64, "c1c2", (1.0,), 1e-4, "f32"),
+    (64, "radial", (0.05, 0.5), 1e-4, "f32"),
+    (66, "c1c2", (1.2,), 1e-4, "f32"),
+    (64, "paper_ellipse", (1.0,), 1e-3, "f32"),
+    (64, "paper_circle", (1.0,), 1e-3, "f32"),
+    (64, "c1c2", (1.0,), 1e-6, "f64"),
+    (128, "c1c2", (1.0,), 1e-2, "f32"),
+])
+def test_full_grid_matches_direct_sum(N, kind, params, tol, precision):
+    """Every output point against the FP64 direct sum (A28 relative l2 <= tol)."""
+    rng = np.random.default_rng(6)
+    f = fi.complex_gaussian(N, rng)
+    fhat = fi.fhat_from_f(f)
+    p = _plan(N, kind, params, tol, precision=precision)
+    u = _apply(p, fhat, precision).ravel()
+    exact = od.direct(N, ref.KINDS[kind], params, fhat, np.arange(N * N))
+    err = ref.rel_l2(u, exact)
+    print("  rel-l2 %.3e  max-abs/max %.3e" % (err, np.max(np.abs(u - exact)) / np.max(np.abs(exact))))
+    assert err <= tol
+    assert np.max(np.abs(u - exact)) <= 10 * tol * np.max(np.abs(exact))
+
+
+def test_small_config_fp64_coronae_full_direct_sum():
+    """N = 64, real white noise, c1/c2 phase, dyadic coronae, FP64, 1e-6 on all 4096 points."""
+    N = 64
+    f = fi.white_noise_real(N, fi.rng_for(0))
+    fhat = fi.fhat_from_f(f)
+    p = _plan(N, "c1c2", (1.0,), 1e-6, precision="f64", partition="coronae")
+    u = _apply(p, fhat, "f64").ravel()
+    exact = od.direct(N, 2, (1.0,), fhat, np.arange(N * N))
+    assert ref.rel_l2(u, exact) <= 1e-6
+
+
+@pytest.mark.parametrize("kind,params", [("c1c2", (1.0,)), ("radial", (0.05, 0.5))])
+@pytest.mark.parametrize("tol", [1e-2, 1e-4, 1e-6])
+def test_n256_tolerance_sweep(kind, params, tol):
+    """N = 256, complex Gaussian f, FP32 data with FP64 phase; 2048 sampled outputs."""
+    N = 256
+    rng = fi.rng_for(1, int(-math.log10(tol)))
+    f = fi.complex_gaussian(N, rng)
+    fhat = fi.fhat_from_f(f)
+    xs = fi.sample_points(N, 2048, rng)
+    p = _plan(N, kind, params, tol)
+    u = _apply(p, fhat).ravel()[xs]
+    exact = od.direct(N, ref.KINDS[kind], params, fhat, xs)
+    err = ref.rel_l2(u, exact)
+    print("  rel-l2 %.3e ranks %d..%d" % (err, p.info()["min_rank"], p.info()["max_rank"]))
+    assert err <= tol
+
+
+def test_n256_all_points_c1c2():
+    """N = 256 c1/c2 at 1e-4 against the direct sum at all 65536 points."""
+    N = 256
+    rng = fi.rng_for(1, 0)
+    f = fi.complex_gaussian(N, rng)
+    fhat = fi.fhat_from_f(f)
+    p = _plan(N, "c1c2", (1.0,), 1e-4)
+    u = _apply(p, fhat).ravel()
+    exact = od.direct(N, 2, (1.0,), fhat, np.arange(N * N))
+    assert ref.rel_l2(u, exact) <= 1e-4
+
+
+# ------------------------------------------------------------------ per wedge (Section 1.3 partition of unity)
+def test_per_wedge_partials_match_direct_sums():
+    N = 64
+    rng = np.random.default_rng(7)
+    fhat = fi.fhat_from_f(fi.complex_gaussian(N, rng))
+    p = _plan(N, "c1c2", (1.0,), 1e-5)
+    ids = p.wedge_map()
+    xs = np.arange(N * N)
+    fd = _dev(fhat)
+    total = np.zeros(N * N, complex)
+    for ell in range(p.L):
+        part = p.apply_wedges(ell, ell + 1, fd)
+        torch.cuda.synchronize()
+        part = part.cpu().numpy().ravel().astype(complex)
+        exact = od.direct(N, 2, (1.0,), fhat, xs, member=ids, only=ell)
+        assert ref.rel_l2(part, exact) < 2e-4, ell
+        total += part
+    full = _apply(p, fhat).ravel()
+    assert ref.rel_l2(total, full) < 1e-6
+
+
+# ------------------------------------------------------------------ batching, determinism, multi-instance
+def test_batch_is_bitwise_a_loop_of_singles():
+    N = 128
+    rng = np.random.default_rng(8)
+    fh = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=6))
+    p = _plan(N, "c1c2", (1.0,), 1e-4, max_batch=4)
+    ub = p.apply(_dev(fh))
+    torch.cuda.synchronize()
+    ub = ub.cpu().numpy()
+    for b in range(6):
+        us = _apply(p, fh[b])
+        assert np.array_equal(ub[b].astype(np.complex128), us)
+
+
+def test_apply_is_deterministic():
+    N = 64
+    fh = fi.fhat_from_f(fi.complex_gaussian(N, np.random.default_rng(9)))
+    p = _plan(N, "radial", (0.05, 0.5), 1e-4)
+    a = _apply(p, fh)
+    b = _apply(p, fh)
+    assert np.array_equal(a, b)
+
+
+def test_multi_instance_matches_singles():
+    from paper_math_0610051_amd import apply_multi
+    rng = np.random.default_rng(10)
+    specs = [(64, "c1c2", (0.7,), 2), (128, "radial", (0.05, 0.5), 1), (96, "c1c2", (1.4,), 3)]
+    plans, fh = [], []
+    for N, kind, params, B in specs:
+        plans.append(_plan(N, kind, params, 1e-4))
+        fh.append(_dev(fi.fhat_from_f(fi.complex_gaussian(N, rng, B=B))))
+    outs = apply_multi(plans, fh)
+    torch.cuda.synchronize()
+    for p, f, u in zip(plans, fh, outs):
+        single = p.apply(f)
+        torch.cuda.synchronize()
+        assert torch.equal(single, u)
+
+
+# ------------------------------------------------------------------ large sizes, sampled outputs
+@pytest.mark.parametrize("N,B", [(512, 2), (1024, 1)])
+def test_large_sizes_sampled(N, B):
+    rng = fi.rng_for(2, 0)
+    fh = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=B))
+    xs = fi.sample_points(N, 384, rng)
+    p = _plan(N, "c1c2", (1.0,), 1e-4)
+    u = p.apply(_dev(fh))
+    torch.cuda.synchronize()
+    u = u.cpu().numpy().reshape(B, N * N)[:, xs]
+    exact = od.direct(N, 2, (1.0,), fh, xs)
+    err = ref.rel_l2(u, exact)
+    print("  N=%d rel-l2 %.3e" % (N, err))
+    assert err <= 1e-4
