@@ -2,6 +2,7 @@
 // device selection and error reporting live here; the plan builder is in
 // plan.hip and the apply kernels in apply.hip.
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -139,6 +140,8 @@ fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, 
     fio_plan_s *P = new (std::nothrow) fio_plan_s();
     if (!P)
         return (set_error("host allocation failed"), FIO_ENOMEM);
+    static std::atomic<unsigned long long> next_serial{1};
+    P->serial = next_serial++;
     P->N = N;
     P->phase.kind = phase->kind;
     std::memcpy(P->phase.p, phase->p, sizeof(P->phase.p));

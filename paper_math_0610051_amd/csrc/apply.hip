@@ -12,33 +12,35 @@
 //
 // Stages 1 and 2 run LDS-resident Stockham transforms; stage 3 is atomic-free:
 // each thread owns one output point and loops over all wedges.
+#include <climits>
+#include <cstring>
+
 #include "apply.hpp"
 
 namespace fio {
 
 // ---------------------------------------------------------------------------
-// Stage 1: window x factor -> box row, FFT along axis 2 (length n2).
-// One workgroup per (wedge, box row, rank chunk); loops over the batch.
+// Stage 1: window x factor -> box row, FFT along axis 2 (length n2, the short
+// side of the box).  One workgroup per (wedge, box row, rank chunk); loops
+// over the batch; in-place LDS transform.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_rows(PlanArgs<T> a, const RowItem *__restrict__ items,
-                                                   const cplx<T> *__restrict__ fhat, long long fstride, int B) {
+__device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it, const cplx<T> *__restrict__ fhat,
+                                          long long fstride, int B) {
+    constexpr int E = kFftLdsBytes / (int)sizeof(cplx<T>) / kFftThreads;
     extern __shared__ unsigned char smem_raw[];
-    cplx<T> *buf0 = reinterpret_cast<cplx<T> *>(smem_raw);
-    const RowItem it = items[blockIdx.x];
+    cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
     const WedgeDev &W = a.wedges[it.l];
     const int n = W.n2, nb = it.tn, q = W.q, B2 = W.B2, lo2 = W.lo2;
     const int tid = threadIdx.x, nt = blockDim.x;
-    cplx<T> *buf1 = buf0 + n * nb;
     const FftPlan *pl = a.fftplans + W.fft2;
-    const int npass = pl->npass;
     const cplx<T> *tw = a.tw + W.tw2;
     const int *map = a.map + W.map_off + (long long)it.k1 * B2;
     const int *omega = a.omega + W.mem_off;
     const cplx<T> *gxi = a.gxi + W.gxi_off + it.t0;
     for (int b = 0; b < B; ++b) {
         for (int i = tid; i < n * nb; i += nt)
-            buf0[i] = cmake<T>(0, 0);
+            buf[i] = cmake<T>(0, 0);
         __syncthreads();
         const cplx<T> *f = fhat + b * fstride;
         for (int i = tid; i < B2 * nb; i += nt) {
@@ -48,50 +50,52 @@ __global__ __launch_bounds__(kThreads) void k_rows(PlanArgs<T> a, const RowItem 
                 int j2 = lo2 + k2;
                 if (j2 < 0)
                     j2 += n;
-                buf0[j2 * nb + t] = cmul(f[omega[m]], gxi[(long long)m * q + t]);
+                buf[j2 * nb + t] = cmul(f[omega[m]], gxi[(long long)m * q + t]);
             }
         }
         __syncthreads();
-        cplx<T> *src = buf0, *dst = buf1;
-        int Ns = 1;
-        for (int p = 0; p < npass; ++p) {
-            const int R = pl->radix[p];
-            stockham_pass<T>(R, src, dst, n, nb, Ns, tw, tid, nt);
-            __syncthreads();
-            cplx<T> *tmp = src;
-            src = dst;
-            dst = tmp;
-            Ns *= R;
-        }
+        fft_inplace<T, E>(buf, pl, n, nb, tw, tid, nt);
         cplx<T> *H = a.H + b * a.H_stride + W.H_off + (long long)it.k1 * n * q + it.t0;
         for (int i = tid; i < n * nb; i += nt) {
             const int j2 = i / nb, t = i - j2 * nb;
-            H[(long long)j2 * q + t] = src[i];
+            H[(long long)j2 * q + t] = buf[i];
         }
         __syncthreads();
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_rows(PlanArgs<T> a, const RowItem *__restrict__ items,
+                                                      const cplx<T> *__restrict__ fhat, long long fstride, int B) {
+    rows_body<T>(a, items[blockIdx.x], fhat, fstride, B);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_rows_multi(const InstArgs<T> *__restrict__ inst,
+                                                            const MultiRowItem *__restrict__ items) {
+    const MultiRowItem m = items[blockIdx.x];
+    const InstArgs<T> &I = inst[m.inst];
+    rows_body<T>(I.a, RowItem{m.l, m.k1, m.t0, m.tn}, I.fhat, (long long)I.a.N * I.a.N, I.B);
+}
+
 // ---------------------------------------------------------------------------
-// Stage 2: FFT along axis 1 (length n1) of nb adjacent transforms
-// tau = j2 * q + t; rows outside the box are the implicit zero padding.
+// Stage 2: FFT along axis 1 (length n1, the long side) of nb adjacent
+// transforms tau = j2 * q + t; rows outside the box are the implicit zero
+// padding.  In-place LDS transform.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cols(PlanArgs<T> a, const ColItem *__restrict__ items) {
+__device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it, int b) {
+    constexpr int E = kFftLdsBytes / (int)sizeof(cplx<T>) / kFftThreads;
     extern __shared__ unsigned char smem_raw[];
-    cplx<T> *buf0 = reinterpret_cast<cplx<T> *>(smem_raw);
-    const ColItem it = items[blockIdx.x];
-    const int b = blockIdx.y;
+    cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
     const WedgeDev &W = a.wedges[it.l];
     const int n = W.n1, nb = it.nb, B1 = W.B1, lo1 = W.lo1;
     const long long rs = (long long)W.n2 * W.q;  // row stride of H and G
     const int tid = threadIdx.x, nt = blockDim.x;
-    cplx<T> *buf1 = buf0 + n * nb;
     const FftPlan *pl = a.fftplans + W.fft1;
-    const int npass = pl->npass;
     const cplx<T> *tw = a.tw + W.tw1;
     for (int i = tid; i < n * nb; i += nt)
-        buf0[i] = cmake<T>(0, 0);
+        buf[i] = cmake<T>(0, 0);
     __syncthreads();
     const cplx<T> *H = a.H + b * a.H_stride + W.H_off + it.tau0;
     for (int i = tid; i < B1 * nb; i += nt) {
@@ -99,25 +103,27 @@ __global__ __launch_bounds__(kThreads) void k_cols(PlanArgs<T> a, const ColItem 
         int j1 = lo1 + k1;
         if (j1 < 0)
             j1 += n;
-        buf0[j1 * nb + c] = H[k1 * rs + c];
+        buf[j1 * nb + c] = H[k1 * rs + c];
     }
     __syncthreads();
-    cplx<T> *src = buf0, *dst = buf1;
-    int Ns = 1;
-    for (int p = 0; p < npass; ++p) {
-        const int R = pl->radix[p];
-        stockham_pass<T>(R, src, dst, n, nb, Ns, tw, tid, nt);
-        __syncthreads();
-        cplx<T> *tmp = src;
-        src = dst;
-        dst = tmp;
-        Ns *= R;
-    }
+    fft_inplace<T, E>(buf, pl, n, nb, tw, tid, nt);
     cplx<T> *G = a.G + b * a.G_stride + W.G_off + it.tau0;
     for (int i = tid; i < n * nb; i += nt) {
         const int j1 = i / nb, c = i - j1 * nb;
-        G[j1 * rs + c] = src[i];
+        G[j1 * rs + c] = buf[i];
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_cols(PlanArgs<T> a, const ColItem *__restrict__ items) {
+    cols_body<T>(a, items[blockIdx.x], blockIdx.y);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_cols_multi(const InstArgs<T> *__restrict__ inst,
+                                                            const MultiColItem *__restrict__ items) {
+    const MultiColItem m = items[blockIdx.x];
+    cols_body<T>(inst[m.inst].a, ColItem{m.l, m.tau0, m.nb, 0}, m.b);
 }
 
 template <typename T>
@@ -133,20 +139,66 @@ __device__ inline void expi_t<double>(double r, double &c, double &s) {
 
 // ---------------------------------------------------------------------------
 // Stage 3: interpolate + modulate + combine over t + accumulate over ell.
-// One thread per output point x; up to 4 right-hand sides per launch share
-// the warped point, kernel weights and gamma^x.  W is the kernel width,
-// QC the rank chunk held in registers.
+// A workgroup owns a kTileX x kTileX tile of output points (one per thread)
+// and loops over the wedges.  For one wedge the stencils of the tile cover a
+// small window of the oversampled grid.  The window is found by a block
+// min/max reduction, with grid coordinates unwrapped around the tile's corner
+// point so that the periodic wrap cannot split it; it is staged into LDS
+// with coalesced row copies and every thread interpolates its point from
+// LDS.  A window larger than the LDS budget (strongly folded warps) is read
+// from the grid directly instead.  Up to kInterpBatch right-hand sides share
+// the warped point, the kernel weights and gamma^x.
 // ---------------------------------------------------------------------------
-template <typename T, int W, int QC>
-__global__ __launch_bounds__(kThreads) void k_interp(PlanArgs<T> a, cplx<T> *__restrict__ u, long long ustride,
-                                                     int B, int bofs, int l0, int l1) {
+// 16-byte unit of the staged window: two complex floats or one complex double.
+template <typename T>
+struct Unit16;
+template <>
+struct Unit16<float> {
+    using type = float4;
+};
+template <>
+struct Unit16<double> {
+    using type = double2;
+};
+
+__device__ inline int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+template <typename T, int W>
+__device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__restrict__ u, long long ustride, int B,
+                                            int bofs, int l0, int l1, int tile) {
+    using U = typename Unit16<T>::type;
+    constexpr int CPU = 16 / (int)sizeof(cplx<T>);  // complex per 16-byte unit (rank pair / single rank)
+    constexpr int kUnits = kInterpLdsBytes / 16;     // window capacity in units
+    constexpr int kOff = kUnits / kThreads;          // staged units of one plane per thread
+    extern __shared__ unsigned char smem_raw[];
+    U *win = reinterpret_cast<U *>(smem_raw);
+    __shared__ int red[kThreads / 64][4];
     const int N = a.N;
-    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (long long)N * N)
-        return;
-    const int n1 = (int)(p / N), n2 = (int)(p - (long long)n1 * N);
+    const int tiles2 = (N + kTileX - 1) / kTileX;
+    const int T1 = (tile / tiles2) * kTileX, T2 = (tile % tiles2) * kTileX;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // a wave covers an 8 x 8 block of the tile and each 16-lane LDS phase a
+    // 4 x 4 block, so that the lanes of one phase read nearby window cells
+    const int grp = lane >> 4, h = lane & 15;
+    const int n1 = T1 + (wave >> 1) * 8 + (grp >> 1) * 4 + (h >> 2);
+    const int n2 = T2 + (wave & 1) * 8 + (grp & 1) * 4 + (h & 3);
+    const bool active = n1 < N && n2 < N;
+    const long long p = (long long)n1 * N + n2;
     const double x1 = (double)n1 / N, x2 = (double)n2 / N;
+    const double r1 = (double)T1 / N, r2 = (double)T2 / N;
     const XCoef c = phase_xcoef(a.phase, x1, x2);
+    const XCoef cr = phase_xcoef(a.phase, r1, r2);
     cplx<T> acc[kInterpBatch];
 #pragma unroll
     for (int b = 0; b < kInterpBatch; ++b)
@@ -155,82 +207,212 @@ __global__ __launch_bounds__(kThreads) void k_interp(PlanArgs<T> a, cplx<T> *__r
         const WedgeDev &wd = a.wedges[l];
         if (wd.q == 0)
             continue;
-        double g1, g2;
+        const int m1 = wd.n1, m2 = wd.n2, q = wd.q, qu = q / CPU;
+        double g1, g2, h1, h2;
         phase_grad(a.phase, c, wd.e1, wd.e2, g1, g2);
+        phase_grad(a.phase, cr, wd.e1, wd.e2, h1, h2);
         const double y1 = x1 + g1, y2 = x2 + g2;
+        const double ry1 = r1 + h1, ry2 = r2 + h2;
         const double yp1 = wd.mt[0] * y1 + wd.mt[1] * y2;
         const double yp2 = wd.mt[2] * y1 + wd.mt[3] * y2;
+        const double k1 = floor(wd.mt[0] * ry1 + wd.mt[1] * ry2);
+        const double k2 = floor(wd.mt[2] * ry1 + wd.mt[3] * ry2);
         double psi = wd.cvec[0] * y1 + wd.cvec[1] * y2;
         psi -= rint(psi);
         T cs, sn;
         expi_t<T>(psi, cs, sn);
-        const int m1 = wd.n1, m2 = wd.n2, q = wd.q;
-        const double u1 = m1 * (yp1 - floor(yp1));
-        const double u2 = m2 * (yp2 - floor(yp2));
-        int j1 = (int)floor(u1 - 0.5 * W) + 1;
-        int j2 = (int)floor(u2 - 0.5 * W) + 1;
+        // grid coordinates unwrapped around the tile's corner point
+        const double u1 = m1 * (yp1 - k1), u2 = m2 * (yp2 - k2);
+        const int j1 = (int)floor(u1 - 0.5 * W) + 1;
+        const int j2 = (int)floor(u2 - 0.5 * W) + 1;
         const T f1 = (T)(u1 - j1), f2 = (T)(u2 - j2);
-        T w2[W];
+        T w1[W], w2[W];
 #pragma unroll
-        for (int i = 0; i < W; ++i)
+        for (int i = 0; i < W; ++i) {
+            w1[i] = es_kernel<T>(f1 - T(i), a.two_over_w, a.beta);
             w2[i] = es_kernel<T>(f2 - T(i), a.two_over_w, a.beta);
-        if (j1 < 0)
-            j1 += m1;
-        if (j2 < 0)
-            j2 += m2;
-        const long long rs = (long long)m2 * q;
+        }
+        // window of the tile's stencils
+        {
+            const int mn1 = wave_min(active ? j1 : INT_MAX), mx1 = wave_max(active ? j1 : INT_MIN);
+            const int mn2 = wave_min(active ? j2 : INT_MAX), mx2 = wave_max(active ? j2 : INT_MIN);
+            if (lane == 0) {
+                red[wave][0] = mn1;
+                red[wave][1] = mx1;
+                red[wave][2] = mn2;
+                red[wave][3] = mx2;
+            }
+        }
+        __syncthreads();
+        int J1 = red[0][0], X1 = red[0][1], J2 = red[0][2], X2 = red[0][3];
+#pragma unroll
+        for (int k = 1; k < kThreads / 64; ++k) {
+            J1 = min(J1, red[k][0]);
+            X1 = max(X1, red[k][1]);
+            J2 = min(J2, red[k][2]);
+            X2 = max(X2, red[k][3]);
+        }
+        __syncthreads();
+        const int F1 = X1 - J1 + W, F2 = X2 - J2 + W;
+        const int S2 = F2 | 1;                   // odd LDS row stride (units) spreads rows over the banks
+        const int plane = F1 * S2;               // units of one rank-pair plane of the window
+        const int ppr = kUnits / plane;          // planes staged per round
+        const bool staged = ppr >= 1 && F1 <= m1 && F2 <= m2;
         const cplx<T> *gxp = a.gx + wd.gx_off + p * q;
         const cplx<T> mod = cmake(cs, sn);
-        for (int b = 0; b < B; ++b) {
-            const cplx<T> *G = a.G + (long long)(bofs + b) * a.G_stride + wd.G_off;
-            cplx<T> v = cmake<T>(0, 0);
-            for (int t0 = 0; t0 < q; t0 += QC) {
-                cplx<T> s[QC];
+        const cplx<T> *G0 = a.G + (long long)bofs * a.G_stride + wd.G_off;
+        if (staged) {
+            // source offsets (complex, rank 0) and window positions of this thread's cells
+            int off[kOff], dst[kOff];
+            int c0 = J2 % m2;
+            if (c0 < 0)
+                c0 += m2;
 #pragma unroll
-                for (int t = 0; t < QC; ++t)
-                    s[t] = cmake<T>(0, 0);
-#pragma unroll 1
-                for (int i1 = 0; i1 < W; ++i1) {
-                    const T wa = es_kernel<T>(f1 - T(i1), a.two_over_w, a.beta);
-                    int r1 = j1 + i1;
-                    if (r1 >= m1)
-                        r1 -= m1;
-                    const cplx<T> *row = G + r1 * rs + t0;
+            for (int k = 0; k < kOff; ++k) {
+                const int e = tid + k * kThreads;
+                off[k] = -1;
+                dst[k] = 0;
+                if (e < F1 * F2) {
+                    const int rr = e / F2, cc = e - rr * F2;
+                    int gr = (J1 + rr) % m1;
+                    if (gr < 0)
+                        gr += m1;
+                    int gc = c0 + cc;
+                    if (gc >= m2)
+                        gc -= m2;
+                    off[k] = (gr * m2 + gc) * q;
+                    dst[k] = rr * S2 + cc;
+                }
+            }
+            const int base = (j1 - J1) * S2 + (j2 - J2);
+            for (int b = 0; b < B; ++b) {
+                const cplx<T> *G = G0 + (long long)b * a.G_stride;
+                cplx<T> v = cmake<T>(0, 0);
+                for (int tu0 = 0; tu0 < qu; tu0 += ppr) {
+                    const int nt = min(ppr, qu - tu0);
+                    for (int tl = 0; tl < nt; ++tl) {
+                        const int tsrc = (tu0 + tl) * CPU;
 #pragma unroll
-                    for (int i2 = 0; i2 < W; ++i2) {
-                        int r2 = j2 + i2;
-                        if (r2 >= m2)
-                            r2 -= m2;
-                        const T wt = wa * w2[i2];
-                        const cplx<T> *cell = row + (long long)r2 * q;
+                        for (int k = 0; k < kOff; ++k)
+                            if (off[k] >= 0)
+                                win[tl * plane + dst[k]] = *reinterpret_cast<const U *>(G + off[k] + tsrc);
+                    }
+                    __syncthreads();
+                    if (active) {
+                        for (int tl = 0; tl < nt; ++tl) {
+                            const U *pw = win + tl * plane + base;
+                            U sum;
+                            if constexpr (CPU == 2)
+                                sum = make_float4(0.f, 0.f, 0.f, 0.f);
+                            else
+                                sum = make_double2(0.0, 0.0);
 #pragma unroll
-                        for (int t = 0; t < QC; ++t) {
-                            if (t0 + t < q) {
-                                const cplx<T> g = cell[t];
-                                s[t].re += wt * g.re;
-                                s[t].im += wt * g.im;
+                            for (int i1 = 0; i1 < W; ++i1) {
+                                const U *pr = pw + i1 * S2;
+                                U rs = pr[0];
+                                rs.x *= w2[0];
+                                rs.y *= w2[0];
+                                if constexpr (CPU == 2) {
+                                    rs.z *= w2[0];
+                                    rs.w *= w2[0];
+                                }
+#pragma unroll
+                                for (int i2 = 1; i2 < W; ++i2) {
+                                    const U g = pr[i2];
+                                    rs.x += w2[i2] * g.x;
+                                    rs.y += w2[i2] * g.y;
+                                    if constexpr (CPU == 2) {
+                                        rs.z += w2[i2] * g.z;
+                                        rs.w += w2[i2] * g.w;
+                                    }
+                                }
+                                sum.x += w1[i1] * rs.x;
+                                sum.y += w1[i1] * rs.y;
+                                if constexpr (CPU == 2) {
+                                    sum.z += w1[i1] * rs.z;
+                                    sum.w += w1[i1] * rs.w;
+                                }
                             }
+                            const U gx = *reinterpret_cast<const U *>(gxp + (tu0 + tl) * CPU);
+                            cfma(v, cmake<T>(gx.x, gx.y), cmake<T>(sum.x, sum.y));
+                            if constexpr (CPU == 2)
+                                cfma(v, cmake<T>(gx.z, gx.w), cmake<T>(sum.z, sum.w));
                         }
                     }
+                    __syncthreads();
                 }
+                const cplx<T> mv = cmul(mod, v);
 #pragma unroll
-                for (int t = 0; t < QC; ++t)
-                    if (t0 + t < q)
-                        cfma(v, gxp[t0 + t], s[t]);
+                for (int bb = 0; bb < kInterpBatch; ++bb)
+                    if (bb == b) {
+                        acc[bb].re += mv.re;
+                        acc[bb].im += mv.im;
+                    }
             }
-            const cplx<T> mv = cmul(mod, v);
+        } else if (active) {
+            // window too large for LDS (strongly folded warp): read the grid directly
+            int g1i = j1 % m1, g2i = j2 % m2;
+            if (g1i < 0)
+                g1i += m1;
+            if (g2i < 0)
+                g2i += m2;
+            for (int b = 0; b < B; ++b) {
+                const cplx<T> *G = G0 + (long long)b * a.G_stride;
+                cplx<T> v = cmake<T>(0, 0);
+                for (int t = 0; t < q; ++t) {
+                    cplx<T> sum = cmake<T>(0, 0);
 #pragma unroll
-            for (int bb = 0; bb < kInterpBatch; ++bb)
-                if (bb == b) {
-                    acc[bb].re += mv.re;
-                    acc[bb].im += mv.im;
+                    for (int i1 = 0; i1 < W; ++i1) {
+                        int r1 = g1i + i1;
+                        if (r1 >= m1)
+                            r1 -= m1;
+                        const cplx<T> *row = G + (long long)r1 * m2 * q + t;
+                        cplx<T> rs = cmake<T>(0, 0);
+#pragma unroll
+                        for (int i2 = 0; i2 < W; ++i2) {
+                            int r2 = g2i + i2;
+                            if (r2 >= m2)
+                                r2 -= m2;
+                            const cplx<T> g = row[(long long)r2 * q];
+                            rs.re += w2[i2] * g.re;
+                            rs.im += w2[i2] * g.im;
+                        }
+                        sum.re += w1[i1] * rs.re;
+                        sum.im += w1[i1] * rs.im;
+                    }
+                    cfma(v, gxp[t], sum);
                 }
+                const cplx<T> mv = cmul(mod, v);
+#pragma unroll
+                for (int bb = 0; bb < kInterpBatch; ++bb)
+                    if (bb == b) {
+                        acc[bb].re += mv.re;
+                        acc[bb].im += mv.im;
+                    }
+            }
         }
     }
+    if (active) {
 #pragma unroll
-    for (int b = 0; b < kInterpBatch; ++b)
-        if (b < B)
-            u[b * ustride + p] = acc[b];
+        for (int b = 0; b < kInterpBatch; ++b)
+            if (b < B)
+                u[b * ustride + p] = acc[b];
+    }
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(kThreads) void k_interp(PlanArgs<T> a, cplx<T> *__restrict__ u, long long ustride,
+                                                     int B, int bofs, int l0, int l1) {
+    interp_body<T, W>(a, u, ustride, B, bofs, l0, l1, blockIdx.x);
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(kThreads) void k_interp_multi(const InstArgs<T> *__restrict__ inst,
+                                                           const MultiTile *__restrict__ tiles) {
+    const MultiTile m = tiles[blockIdx.x];
+    const InstArgs<T> &I = inst[m.inst];
+    interp_body<T, W>(I.a, I.u + (long long)m.b0 * I.a.N * I.a.N, (long long)I.a.N * I.a.N, m.nb, m.b0, 0, I.a.L,
+                      m.tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -263,14 +445,8 @@ PlanArgs<T> make_args(const fio_plan_s *P) {
 template <typename T, int W>
 static hipError_t launch_interp_w(const fio_plan_s *P, const PlanArgs<T> &a, cplx<T> *u, long long ustride, int B,
                                   int bofs, int l0, int l1, hipStream_t s) {
-    const long long npts = (long long)P->N * P->N;
-    const unsigned grid = (unsigned)((npts + kThreads - 1) / kThreads);
-    if (P->qmax <= 4)
-        k_interp<T, W, 4><<<grid, kThreads, 0, s>>>(a, u, ustride, B, bofs, l0, l1);
-    else if (P->qmax <= 8)
-        k_interp<T, W, 8><<<grid, kThreads, 0, s>>>(a, u, ustride, B, bofs, l0, l1);
-    else
-        k_interp<T, W, 16><<<grid, kThreads, 0, s>>>(a, u, ustride, B, bofs, l0, l1);
+    const int tiles = (P->N + kTileX - 1) / kTileX;
+    k_interp<T, W><<<(unsigned)(tiles * tiles), kThreads, kInterpLdsBytes, s>>>(a, u, ustride, B, bofs, l0, l1);
     return hipGetLastError();
 }
 
@@ -326,14 +502,14 @@ static hipError_t apply_t(fio_plan_s *P, int B, const void *fhat, void *u, hipSt
         const int bc = std::min(P->bchunk, B - b0);
         if (r1 > r0) {
             StageTimer tm(P, 0, s);
-            k_rows<T><<<r1 - r0, kThreads, P->lds_rows, s>>>(a, P->d_rows + r0, f + b0 * NN, NN, bc);
+            k_rows<T><<<r1 - r0, kFftThreads, P->lds_rows, s>>>(a, P->d_rows + r0, f + b0 * NN, NN, bc);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess)
                 return e;
         }
         if (c1 > c0) {
             StageTimer tm(P, 1, s);
-            k_cols<T><<<dim3(c1 - c0, bc), kThreads, P->lds_cols, s>>>(a, P->d_cols + c0);
+            k_cols<T><<<dim3(c1 - c0, bc), kFftThreads, P->lds_cols, s>>>(a, P->d_cols + c0);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess)
                 return e;
@@ -372,8 +548,74 @@ hipError_t zero_fill(void *ptr, size_t bytes, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T, int W>
+static void launch_multi_w(const MultiLaunch &ml, hipStream_t s) {
+    const InstArgs<T> *I = static_cast<const InstArgs<T> *>(ml.inst);
+    if (ml.nrows)
+        k_rows_multi<T><<<ml.nrows, kFftThreads, ml.lds_rows, s>>>(I, ml.rows);
+    if (ml.ncols)
+        k_cols_multi<T><<<ml.ncols, kFftThreads, ml.lds_cols, s>>>(I, ml.cols);
+    if (ml.ntiles)
+        k_interp_multi<T, W><<<ml.ntiles, kThreads, kInterpLdsBytes, s>>>(I, ml.tiles);
+}
+
+template <typename T>
+static hipError_t launch_multi_t(const MultiLaunch &ml, hipStream_t s) {
+    switch (ml.w) {
+    case 4: launch_multi_w<T, 4>(ml, s); break;
+    case 5: launch_multi_w<T, 5>(ml, s); break;
+    case 6: launch_multi_w<T, 6>(ml, s); break;
+    case 7: launch_multi_w<T, 7>(ml, s); break;
+    case 8: launch_multi_w<T, 8>(ml, s); break;
+    case 10: launch_multi_w<T, 10>(ml, s); break;
+    case 12: launch_multi_w<T, 12>(ml, s); break;
+    case 14: launch_multi_w<T, 14>(ml, s); break;
+    case 16: launch_multi_w<T, 16>(ml, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t multi_launch(const MultiLaunch &ml, hipStream_t s) {
+    return ml.precision == FIO_F64 ? launch_multi_t<double>(ml, s) : launch_multi_t<float>(ml, s);
+}
+
+template <typename T>
+static void fill_inst_t(const fio_plan_s *P, const void *fhat, void *u, int B, void *out) {
+    InstArgs<T> I;
+    I.a = make_args<T>(P);
+    I.fhat = static_cast<const cplx<T> *>(fhat);
+    I.u = static_cast<cplx<T> *>(u);
+    I.B = B;
+    std::memcpy(out, &I, sizeof(I));
+}
+
+size_t inst_args_size(int precision) {
+    return precision == FIO_F64 ? sizeof(InstArgs<double>) : sizeof(InstArgs<float>);
+}
+
+void fill_inst_args(const fio_plan_s *P, const void *fhat, void *u, int B, void *out) {
+    if (P->precision == FIO_F64)
+        fill_inst_t<double>(P, fhat, u, B, out);
+    else
+        fill_inst_t<float>(P, fhat, u, B, out);
+}
+
+template <typename T>
+static hipError_t set_lds_limits_multi() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rows_multi<T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
+    if (e != hipSuccess)
+        return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cols_multi<T>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
+}
+
 hipError_t apply_prepare(fio_plan_s *P) {
-    return P->precision == FIO_F64 ? set_lds_limits<double>() : set_lds_limits<float>();
+    hipError_t e = P->precision == FIO_F64 ? set_lds_limits<double>() : set_lds_limits<float>();
+    if (e != hipSuccess)
+        return e;
+    return P->precision == FIO_F64 ? set_lds_limits_multi<double>() : set_lds_limits_multi<float>();
 }
 
 hipError_t apply_launch(fio_plan_s *P, int B, const void *fhat, void *u, hipStream_t s, int l0, int l1) {

@@ -8,9 +8,44 @@
 namespace fio {
 
 constexpr int kThreads = 256;       // workgroup size of every apply kernel
-constexpr int kInterpBatch = 4;     // right-hand sides per interpolation launch
-constexpr int kMaxLdsBytes = 131072;  // two ping-pong FFT buffers per workgroup
+constexpr int kInterpBatch = 8;     // right-hand sides per interpolation launch
+constexpr int kTileX = 16;          // interpolation tile: kTileX x kTileX output points per workgroup
+constexpr int kInterpLdsBytes = 32768;  // LDS window of one wedge's grid per interpolation workgroup
+constexpr int kMaxLdsBytes = 131072;  // largest dynamic LDS request of any apply kernel
+constexpr int kFftThreads = 1024;     // workgroup size of the two FFT stages
+constexpr int kFftLdsBytes = 65536;   // in-place FFT buffer of one workgroup
 constexpr int kInterpWidths[] = {4, 5, 6, 7, 8, 10, 12, 14, 16};
+
+// Per-instance arguments of the multi-instance kernels.
+template <typename T>
+struct InstArgs {
+    PlanArgs<T> a;
+    const cplx<T> *fhat;
+    cplx<T> *u;
+    int B;
+};
+struct MultiRowItem {
+    int inst, l, k1, t0, tn, pad;
+};
+struct MultiColItem {
+    int inst, l, tau0, nb, b, pad;
+};
+struct MultiTile {
+    int inst, tile, b0, nb;
+};
+// One fused launch per stage over every instance, wedge and right-hand side.
+struct MultiLaunch {
+    int precision = FIO_F32, w = 0;
+    const void *inst = nullptr;  // device array of InstArgs<T>
+    const MultiRowItem *rows = nullptr;
+    const MultiColItem *cols = nullptr;
+    const MultiTile *tiles = nullptr;
+    unsigned nrows = 0, ncols = 0, ntiles = 0;
+    size_t lds_rows = 0, lds_cols = 0;
+};
+hipError_t multi_launch(const MultiLaunch &ml, hipStream_t s);
+size_t inst_args_size(int precision);
+void fill_inst_args(const fio_plan_s *P, const void *fhat, void *u, int B, void *out);
 
 hipError_t apply_prepare(fio_plan_s *P);
 // Zero `bytes` (a multiple of 8) with a fill kernel on stream s (no memset node).

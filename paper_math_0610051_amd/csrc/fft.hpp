@@ -221,4 +221,80 @@ __host__ __device__ inline void stockham_pass(int R, const cplx<T> *in, cplx<T> 
     }
 }
 
+#ifdef __HIP_DEVICE_COMPILE__
+#define FIO_BARRIER() __syncthreads()
+#else
+#define FIO_BARRIER() ((void)0)
+#endif
+
+// In-place Stockham pass on a single LDS buffer: every worker reads and
+// transforms its butterflies into registers, the workgroup synchronises, and
+// the results are written back (then synchronises again).  KB bounds the
+// butterflies per worker: (n / R) * nb <= KB * nthreads must hold.
+template <typename T, int R, int KB>
+__device__ __forceinline__ void stockham_pass_inplace(cplx<T> *buf, int n, int nb, int Ns, const cplx<T> *tw, int tid,
+                                             int nthreads) {
+    const int m = n / R;
+    const int total = m * nb;
+    cplx<T> v[KB][R];
+    int dst[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int w = tid + k * nthreads;
+        dst[k] = -1;
+        if (w < total) {
+            const int b = w % nb;
+            const int j = w / nb;
+            const int kk = j % Ns;
+            const int tstep = (n / (Ns * R)) * kk;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const cplx<T> x = buf[(j + r * m) * nb + b];
+                v[k][r] = (r == 0 || kk == 0) ? x : cmul(x, tw[r * tstep]);
+            }
+            dft_small<T, R>(v[k]);
+            dst[k] = ((j / Ns) * Ns * R + kk) * nb + b;
+        }
+    }
+    FIO_BARRIER();
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        if (dst[k] >= 0) {
+#pragma unroll
+            for (int s = 0; s < R; ++s)
+                buf[dst[k] + s * Ns * nb] = v[k][s];
+        }
+    FIO_BARRIER();
+}
+
+// All passes of a length-n transform of nb interleaved sequences in place;
+// E = elements per worker the buffer holds at most (n * nb <= E * nthreads).
+template <typename T, int E>
+__device__ __forceinline__ void fft_inplace(cplx<T> *buf, const FftPlan *pl, int n, int nb, const cplx<T> *tw, int tid,
+                                   int nthreads) {
+    int Ns = 1;
+    const int npass = pl->npass;
+    for (int p = 0; p < npass; ++p) {
+        const int R = pl->radix[p];
+        switch (R) {
+        case 8:
+            stockham_pass_inplace<T, 8, (E + 7) / 8>(buf, n, nb, Ns, tw, tid, nthreads);
+            break;
+        case 4:
+            stockham_pass_inplace<T, 4, (E + 3) / 4>(buf, n, nb, Ns, tw, tid, nthreads);
+            break;
+        case 2:
+            stockham_pass_inplace<T, 2, (E + 1) / 2>(buf, n, nb, Ns, tw, tid, nthreads);
+            break;
+        case 3:
+            stockham_pass_inplace<T, 3, (E + 2) / 3>(buf, n, nb, Ns, tw, tid, nthreads);
+            break;
+        default:
+            stockham_pass_inplace<T, 5, (E + 4) / 5>(buf, n, nb, Ns, tw, tid, nthreads);
+            break;
+        }
+        Ns *= R;
+    }
+}
+
 }  // namespace fio

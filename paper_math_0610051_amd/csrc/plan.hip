@@ -114,13 +114,22 @@ void wedge_geometry(int N, WedgeHost &W) {
             W.xc[1] = mn2 + W.B[1] / 2;
         }
     }
+    // axis 1 is the long side of the box (its FFT runs in the column stage);
+    // swapping the rows of M keeps it unimodular (determinant -1)
+    if (W.B[1] > W.B[0]) {
+        std::swap(W.M[0], W.M[2]);
+        std::swap(W.M[1], W.M[3]);
+        std::swap(W.B[0], W.B[1]);
+        std::swap(W.xc[0], W.xc[1]);
+    }
     W.lo[0] = -(W.B[0] / 2);
     W.lo[1] = -(W.B[1] / 2);
-    // M has determinant 1: inverse [[d, -b], [-c, a]]
-    W.Minv[0] = W.M[3];
-    W.Minv[1] = -W.M[1];
-    W.Minv[2] = -W.M[2];
-    W.Minv[3] = W.M[0];
+    // inverse of a unimodular [[a, b], [c, d]]: [[d, -b], [-c, a]] / det
+    const int det = W.M[0] * W.M[3] - W.M[1] * W.M[2];
+    W.Minv[0] = W.M[3] * det;
+    W.Minv[1] = -W.M[1] * det;
+    W.Minv[2] = -W.M[2] * det;
+    W.Minv[3] = W.M[0] * det;
 }
 
 // ---------------------------------------------------------------------------
@@ -720,7 +729,7 @@ fio_status build_plan(fio_plan_s *P) {
     }
     // 4. layout
     P->esize = P->precision == FIO_F64 ? 16 : 8;
-    const long long cap = kMaxLdsBytes / (2 * (long long)P->esize);  // complex elements per FFT buffer
+    const long long cap = kFftLdsBytes / (long long)P->esize;  // complex elements of the in-place FFT buffer
     P->qmax = 0;
     P->wdev.assign(P->L, WedgeDev());
     long long map_off = 0, mem_off = 0, gxi_off = 0, gx_off = 0, H_off = 0, G_off = 0;
@@ -777,13 +786,16 @@ fio_status build_plan(fio_plan_s *P) {
         for (int k1 = 0; k1 < W.B[0]; ++k1)
             for (int t0 = 0; t0 < W.qpad; t0 += tn)
                 P->rows.push_back(RowItem{l, k1, t0, std::min(tn, W.qpad - t0)});
-        lds_rows = std::max(lds_rows, (size_t)2 * W.n[1] * tn * P->esize);
+        lds_rows = std::max(lds_rows, (size_t)W.n[1] * tn * P->esize);
         // stage-2 items: chunks of adjacent transforms tau = j2 * q + t
+        // adjacent transforms per item: a power of two (cheap index math) filling the buffer
         const long long ntau = (long long)W.n[1] * W.qpad;
-        const int nb = (int)std::max<long long>(1, std::min<long long>(ntau, cap / W.n[0]));
+        int nb = 1;
+        while (2LL * nb * W.n[0] <= cap && 2LL * nb <= ntau && nb < 64)
+            nb *= 2;
         for (long long t0 = 0; t0 < ntau; t0 += nb)
             P->cols.push_back(ColItem{l, (int)t0, (int)std::min<long long>(nb, ntau - t0), 0});
-        lds_cols = std::max(lds_cols, (size_t)2 * W.n[0] * nb * P->esize);
+        lds_cols = std::max(lds_cols, (size_t)W.n[0] * nb * P->esize);
     }
     P->row_first[P->L] = (int)P->rows.size();
     P->col_first[P->L] = (int)P->cols.size();

@@ -78,6 +78,8 @@ struct WedgeHost {
 }  // namespace fio
 
 struct fio_plan_s {
+    unsigned long long serial = 0;  // unique per plan built in this process
+    void *multi_state = nullptr;    // cached multi-instance launch owned by this plan
     int N = 0, L = 0, precision = FIO_F32, device = 0;
     fio::Phase phase{};
     double tol = 0;
