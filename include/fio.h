@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct fio_plan_s *fio_plan_t;
+typedef struct fio_learned_s *fio_learned_t;
 
 typedef enum {
     FIO_OK = 0,
@@ -186,6 +187,46 @@ const char *fio_last_error(void);
  * interleaved) by cyclic Jacobi; w: n eigenvalues in descending order, V:
  * n x n eigenvectors as columns (row-major). */
 fio_status fio_host_eigh(int n, const double *A, double *w, double *V);
+
+/* ---------------------------------------------------------------------------
+ * Learned spatial factors.  A network maps (x1, x2, theta_ell, s) through a
+ * fixed periodic feature map (16 inputs), three hidden layers of width 128
+ * (tanh form of GELU) and 32 outputs to 16 complex spatial factors alpha_t(x)
+ * of wedge ell at phase scale s (the family's p0).  Weights are FP32 masters
+ * fed to the BF16 matrix cores with FP32 accumulation; training and inference
+ * run on the device that is current at creation.  Its targets are the
+ * factors of the randomized separation (Section 3.3) with one column sample
+ * per wedge shared by all training scales: alpha*_s(x) = A_s(x, C) V / s1,
+ * V the leading 16 eigenvectors of the Gram matrix of A_s(:, C) summed over
+ * the scales.  A plan built with opt.learned = this network (factor_mode
+ * AUTO or LEARNED, equiangular wedges, FP32, same N, wedge count and phase
+ * kind) takes gamma^x from the network and refits gamma^xi = alpha_[R]^+ A_[R]
+ * on sampled rows; if an s x s estimate of the separation error exceeds half
+ * the tolerance, AUTO falls back to the exact separation (fio_plan_info's
+ * fallback flag) and LEARNED fails with FIO_EACCURACY.
+ * ------------------------------------------------------------------------- */
+fio_status fio_learned_create(int N, const fio_phase *family, int n_wedges /* 0 = default L */,
+                              unsigned long long seed, fio_learned_t *out);
+/* Training data: x_samples grid points per (scale, wedge), r_cols sampled columns per wedge. */
+fio_status fio_learned_generate(fio_learned_t m, int nscales, const double *scales, int x_samples, int r_cols);
+/* Adam on minibatches of `batch` samples (a multiple of 64), learning rate
+ * decaying from lr to lr_final on a cosine; *final_loss = last minibatch loss. */
+fio_status fio_learned_train(fio_learned_t m, int steps, int batch, double lr, double lr_final, double *final_loss);
+/* Mean loss over the current training data (e.g. generated for held-out scales). */
+fio_status fio_learned_eval(fio_learned_t m, double *loss);
+/* Read (get = 1) or write (get = 0) the FP32 parameters: W1, b1, ..., W4, b4,
+ * W row-major [in][out]; n must equal fio_learned_param_count(). */
+fio_status fio_learned_params(fio_learned_t m, int get, float *params, int n);
+int fio_learned_param_count(void);
+/* Forward pass on n feature rows (host arrays, n x 16 in, n x 32 out). */
+fio_status fio_learned_forward(fio_learned_t m, int n, const float *feat, float *out);
+/* One backward pass of the mean squared error on n rows (n a multiple of 64):
+ * flat gradients in the parameter order (no update) and the loss. */
+fio_status fio_learned_grads(fio_learned_t m, int n, const float *feat, const float *target, float *grads,
+                             double *loss);
+fio_status fio_learned_save(fio_learned_t m, const char *path);
+fio_status fio_learned_load(const char *path, fio_learned_t *out);
+fio_status fio_learned_destroy(fio_learned_t m);
 
 /* Library version string. */
 const char *fio_version(void);

@@ -4,7 +4,7 @@ The compute path is the HIP library libfio.so (C ABI in include/fio.h);
 `fio` is its ctypes binding.  Build it with `python -m
 paper_math_0610051_amd.build` or `__graft_entry__.build()`.
 """
-from .fio import (FioError, Plan, apply_multi, host_eigh, load_library, make_phase,  # noqa: F401
+from .fio import (FioError, Learned, Plan, apply_multi, host_eigh, load_library, make_phase,  # noqa: F401
                   PHASE_KINDS)
 
-__all__ = ["FioError", "Plan", "apply_multi", "host_eigh", "load_library", "make_phase", "PHASE_KINDS"]
+__all__ = ["FioError", "Learned", "Plan", "apply_multi", "host_eigh", "load_library", "make_phase", "PHASE_KINDS"]

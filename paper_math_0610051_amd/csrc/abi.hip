@@ -55,11 +55,7 @@ static void free_plan(fio_plan_s *P) {
     if (!P)
         return;
     drop_events(P);
-    void *bufs[] = {P->d_wedges, P->d_fftplans, P->d_rows, P->d_cols, P->d_map, P->d_omega,
-                    P->d_gxi,    P->d_gx,       P->d_tw,   P->d_H,    P->d_G};
-    for (void *b : bufs)
-        if (b)
-            (void)hipFree(b);
+    release_layout(P);
     multi_release(P);
     delete P;
 }

@@ -22,6 +22,7 @@
 #include "apply.hpp"
 #include "errors.hpp"
 #include "linalg.hpp"
+#include "learned.hpp"
 #include "plan_build.hpp"
 
 namespace fio {
@@ -419,6 +420,72 @@ static std::vector<I> sample_distinct(I n, int k, uint64_t &state) {
 template std::vector<int> sample_distinct<int>(int, int, uint64_t &);
 template std::vector<long long> sample_distinct<long long>(long long, int, uint64_t &);
 
+std::vector<int> sample_members(int n, int k, uint64_t &state) { return sample_distinct<int>(n, k, state); }
+
+// Gram matrix A_C^H A_C (r x r, full Hermitian) of the residual kernel columns
+// at frequencies `cols` over every grid point, reduced on the GPU in FP64.
+// d_xcoef (N^2) is filled with the phase's per-point coefficients when fill_xcoef.
+fio_status gram_of_columns(const Phase &ph, int N, double2 *d_xcoef, double theta, const std::vector<double2> &cols,
+                           DeviceScratch &scr, std::vector<zd> &G, bool fill_xcoef) {
+    const long long NN = (long long)N * N;
+    const int rc = (int)cols.size();
+    if (fill_xcoef) {
+        k_xcoef<<<(unsigned)((NN + 255) / 256), 256>>>(ph, N, d_xcoef);
+        FIO_HIP_TRY(hipGetLastError());
+    }
+    FIO_HIP_TRY(scr.ensure_cols(rc));
+    FIO_HIP_TRY(hipMemcpy(scr.cols, cols.data(), rc * sizeof(double2), hipMemcpyHostToDevice));
+    const int nt = (rc + kGramTile - 1) / kGramTile;
+    const int nblk = (int)std::min<long long>(256, (NN + 4095) / 4096);
+    const long long rpb = (NN + nblk - 1) / nblk;
+    FIO_HIP_TRY(scr.ensure_partial((size_t)nblk * rc * rc, (size_t)rc * rc));
+    k_gram<<<dim3(nblk, nt, nt), 256>>>(ph, d_xcoef, NN, std::cos(theta), std::sin(theta), scr.cols, rc, rpb,
+                                        scr.partial);
+    FIO_HIP_TRY(hipGetLastError());
+    k_gram_reduce<<<(rc * rc + 255) / 256, 256>>>(scr.partial, nblk, rc, scr.gram);
+    FIO_HIP_TRY(hipGetLastError());
+    std::vector<double2> g((size_t)rc * rc);
+    FIO_HIP_TRY(hipMemcpy(g.data(), scr.gram, (size_t)rc * rc * sizeof(double2), hipMemcpyDeviceToHost));
+    G.assign((size_t)rc * rc, zd(0, 0));
+    for (int i = 0; i < rc; ++i)
+        for (int j = i; j < rc; ++j) {
+            G[(size_t)i * rc + j] = zd(g[(size_t)i * rc + j].x, g[(size_t)i * rc + j].y);
+            G[(size_t)j * rc + i] = std::conj(G[(size_t)i * rc + j]);
+        }
+    return FIO_OK;
+}
+
+// s x s estimate of the relative separation error (Section 4): U at rows Gam
+// from `ugam(i, t)`, T at columns Del as P A_[R, Del], A exactly on the host.
+static double separation_estimate(const fio_plan_s *P, const WedgeHost &W, const std::vector<long long> &Gam,
+                                  const std::vector<int> &Del, const std::vector<zd> &UG) {
+    const int N = P->N, h = N / 2, q = W.q;
+    const int rr = (int)W.R.size(), sg = (int)Gam.size(), sd = (int)Del.size();
+    const double e1 = std::cos(W.theta), e2 = std::sin(W.theta);
+    std::vector<zd> TD((size_t)q * sd, zd(0, 0));
+    for (int j = 0; j < sd; ++j) {
+        const int om = W.members[Del[j]];
+        const double k1 = om / N - h, k2 = om % N - h;
+        for (int i = 0; i < rr; ++i) {
+            const zd a = host_residual(P->phase, N, W.R[i], e1, e2, k1, k2);
+            for (int t = 0; t < q; ++t)
+                TD[(size_t)t * sd + j] += W.P[(size_t)t * rr + i] * a;
+        }
+    }
+    double num = 0, den = 0;
+    for (int i = 0; i < sg; ++i)
+        for (int j = 0; j < sd; ++j) {
+            const int om = W.members[Del[j]];
+            const zd a = host_residual(P->phase, N, Gam[i], e1, e2, om / N - h, om % N - h);
+            zd v(0, 0);
+            for (int t = 0; t < q; ++t)
+                v += UG[(size_t)i * q + t] * TD[(size_t)t * sd + j];
+            num += std::norm(a - v);
+            den += std::norm(a);
+        }
+    return std::sqrt(num / std::max(den, 1e-300));
+}
+
 // Randomized separation of one wedge (Section 3.3) with verification.
 fio_status separate_wedge(fio_plan_s *P, int l, const double2 *d_xcoef, DeviceScratch &scr) {
     WedgeHost &W = P->wedges[l];
@@ -442,25 +509,11 @@ fio_status separate_wedge(fio_plan_s *P, int l, const double2 *d_xcoef, DeviceSc
             const int om = W.members[W.C[c]];
             cols[c] = make_double2(om / N - h, om % N - h);
         }
-        // --- Gram of A_[C] on the GPU
-        FIO_HIP_TRY(scr.ensure_cols(rc));
-        FIO_HIP_TRY(hipMemcpy(scr.cols, cols.data(), rc * sizeof(double2), hipMemcpyHostToDevice));
-        const int nt = (rc + kGramTile - 1) / kGramTile;
-        const int nblk = (int)std::min<long long>(256, (NN + 4095) / 4096);
-        const long long rpb = (NN + nblk - 1) / nblk;
-        FIO_HIP_TRY(scr.ensure_partial((size_t)nblk * rc * rc, (size_t)rc * rc));
-        k_gram<<<dim3(nblk, nt, nt), 256>>>(P->phase, d_xcoef, NN, e1, e2, scr.cols, rc, rpb, scr.partial);
-        FIO_HIP_TRY(hipGetLastError());
-        k_gram_reduce<<<(rc * rc + 255) / 256, 256>>>(scr.partial, nblk, rc, scr.gram);
-        FIO_HIP_TRY(hipGetLastError());
-        std::vector<double2> g(rc * rc);
-        FIO_HIP_TRY(hipMemcpy(g.data(), scr.gram, rc * rc * sizeof(double2), hipMemcpyDeviceToHost));
-        std::vector<zd> G((size_t)rc * rc);
-        for (int i = 0; i < rc; ++i)
-            for (int j = i; j < rc; ++j) {
-                G[(size_t)i * rc + j] = zd(g[i * rc + j].x, g[i * rc + j].y);
-                G[(size_t)j * rc + i] = std::conj(G[(size_t)i * rc + j]);
-            }
+        // --- Gram of A_[C] on the GPU (FP64), eigen-decomposition on the host
+        std::vector<zd> G;
+        fio_status gs = gram_of_columns(P->phase, N, const_cast<double2 *>(d_xcoef), W.theta, cols, scr, G, false);
+        if (gs != FIO_OK)
+            return gs;
         std::vector<double> lam;
         std::vector<zd> V;
         eigh_jacobi(rc, G, lam, V);
@@ -495,34 +548,14 @@ fio_status separate_wedge(fio_plan_s *P, int l, const double2 *d_xcoef, DeviceSc
         const int sg = (int)std::min<long long>(sv, NN), sd = std::min(sv, nmem);
         std::vector<long long> Gam = sample_distinct<long long>(NN, sg, state);
         std::vector<int> Del = sample_distinct<int>(nmem, sd, state);
-        std::vector<zd> UG((size_t)sg * q, zd(0, 0)), TD((size_t)q * sd, zd(0, 0));
+        std::vector<zd> UG((size_t)sg * q, zd(0, 0));
         for (int i = 0; i < sg; ++i)
             for (int c = 0; c < rc; ++c) {
                 const zd a = host_residual(P->phase, N, Gam[i], e1, e2, cols[c].x, cols[c].y);
                 for (int t = 0; t < q; ++t)
                     UG[(size_t)i * q + t] += a * W.Z[(size_t)c * q + t];
             }
-        for (int j = 0; j < sd; ++j) {
-            const int om = W.members[Del[j]];
-            const double k1 = om / N - h, k2 = om % N - h;
-            for (int i = 0; i < rr; ++i) {
-                const zd a = host_residual(P->phase, N, W.R[i], e1, e2, k1, k2);
-                for (int t = 0; t < q; ++t)
-                    TD[(size_t)t * sd + j] += W.P[(size_t)t * rr + i] * a;
-            }
-        }
-        double num = 0, den = 0;
-        for (int i = 0; i < sg; ++i)
-            for (int j = 0; j < sd; ++j) {
-                const int om = W.members[Del[j]];
-                const zd a = host_residual(P->phase, N, Gam[i], e1, e2, om / N - h, om % N - h);
-                zd s(0, 0);
-                for (int t = 0; t < q; ++t)
-                    s += UG[(size_t)i * q + t] * TD[(size_t)t * sd + j];
-                num += std::norm(a - s);
-                den += std::norm(a);
-            }
-        W.sep_err = std::sqrt(num / std::max(den, 1e-300));
+        W.sep_err = separation_estimate(P, W, Gam, Del, UG);
         if (W.sep_err <= target || attempt == 9)
             return FIO_OK;
         // the estimate missed the target: tighten the threshold and, while
@@ -571,8 +604,10 @@ DeviceScratch::~DeviceScratch() {
 // ---------------------------------------------------------------------------
 // Device storage of factors, tables and workspace
 // ---------------------------------------------------------------------------
+// gamma^xi = scale * (P A_[R]) for every member (and gamma^x = A_[C] Z for
+// every grid point when exact_x), evaluated in FP64 and stored as T.
 template <typename T>
-static fio_status store_factors(fio_plan_s *P, const double2 *d_xcoef) {
+static fio_status store_factors(fio_plan_s *P, const double2 *d_xcoef, bool exact_x) {
     const int N = P->N;
     const long long NN = (long long)N * N;
     const int h = N / 2;
@@ -610,17 +645,18 @@ static fio_status store_factors(fio_plan_s *P, const double2 *d_xcoef) {
             continue;
         const double e1 = std::cos(W.theta), e2 = std::sin(W.theta);
         const int rc = (int)W.C.size(), rr = (int)W.R.size();
-        // gamma^x
-        std::vector<double2> cols(rc);
-        for (int c = 0; c < rc; ++c) {
-            const int om = W.members[W.C[c]];
-            cols[c] = make_double2(om / N - h, om % N - h);
+        if (exact_x) {
+            std::vector<double2> cols(rc);
+            for (int c = 0; c < rc; ++c) {
+                const int om = W.members[W.C[c]];
+                cols[c] = make_double2(om / N - h, om % N - h);
+            }
+            FIO_HIP_TRY(hipMemcpy(d_cols, cols.data(), rc * sizeof(double2), hipMemcpyHostToDevice));
+            FIO_HIP_TRY(hipMemcpy(d_mat, W.Z.data(), W.Z.size() * sizeof(double2), hipMemcpyHostToDevice));
+            k_gamma_x<T><<<(unsigned)((NN + 255) / 256), 256>>>(P->phase, d_xcoef, NN, e1, e2, d_cols, rc, d_mat, W.q,
+                                                                W.qpad, gx + D.gx_off);
+            FIO_HIP_TRY(hipGetLastError());
         }
-        FIO_HIP_TRY(hipMemcpy(d_cols, cols.data(), rc * sizeof(double2), hipMemcpyHostToDevice));
-        FIO_HIP_TRY(hipMemcpy(d_mat, W.Z.data(), W.Z.size() * sizeof(double2), hipMemcpyHostToDevice));
-        k_gamma_x<T><<<(unsigned)((NN + 255) / 256), 256>>>(P->phase, d_xcoef, NN, e1, e2, d_cols, rc, d_mat, W.q,
-                                                            W.qpad, gx + D.gx_off);
-        FIO_HIP_TRY(hipGetLastError());
         // gamma^xi with deconvolution and 1/N
         std::vector<double4> rows(rr);
         for (int i = 0; i < rr; ++i) {
@@ -650,14 +686,10 @@ static fio_status store_factors(fio_plan_s *P, const double2 *d_xcoef) {
     return FIO_OK;
 }
 
-fio_status build_plan(fio_plan_s *P) {
-    using clock = std::chrono::steady_clock;
-    const auto t_start = clock::now();
+// Partition, NUFFT kernel, shears, boxes, grids and FFT plans.
+static fio_status plan_geometry(fio_plan_s *P) {
     const int N = P->N;
     const long long NN = (long long)N * N;
-    const int h = N / 2;
-    FIO_HIP_TRY(hipGetDevice(&P->device));
-    // 1. partition
     std::vector<double> thetas;
     if (P->opt.partition == FIO_PART_CORONAE) {
         partition_coronae(N, P->wedge_of, thetas);
@@ -673,7 +705,6 @@ fio_status build_plan(fio_plan_s *P) {
         P->wedges[l].theta = thetas[l];
     for (long long i = 0; i < NN; ++i)
         P->wedges[P->wedge_of[i]].members.push_back((int)i);
-    // 2. NUFFT parameters and geometry
     P->sigma = P->opt.sigma > 0 ? P->opt.sigma : 2.0;
     es_parameters(P->tol * P->opt.nufft_tol_frac, P->sigma, P->opt.kernel_width, P->w, P->beta);
     std::map<int, int> fft_index;
@@ -697,6 +728,7 @@ fio_status build_plan(fio_plan_s *P) {
         wedge_geometry(N, W);
         for (int d = 0; d < 2; ++d) {
             W.n[d] = fft_nice_size(std::max((int)std::ceil(P->sigma * W.B[d]), 2 * P->w));
+            W.fft[d] = fft_for(W.n[d]);
         }
         W.dec1.resize(W.B[0]);
         W.dec2.resize(W.B[1]);
@@ -705,33 +737,35 @@ fio_status build_plan(fio_plan_s *P) {
         for (int i = 0; i < W.B[1]; ++i)
             W.dec2[i] = 1.0 / es_fourier(P->w, P->beta, (double)(W.lo[1] + i) / W.n[1]);
     }
-    // 3. randomized separation
-    double2 *d_xcoef = nullptr;
-    FIO_HIP_TRY(hipMalloc(&d_xcoef, NN * sizeof(double2)));
-    struct XGuard {
-        double2 *p;
-        ~XGuard() {
-            if (p)
-                (void)hipFree(p);
-        }
-    } xg{d_xcoef};
-    k_xcoef<<<(unsigned)((NN + 255) / 256), 256>>>(P->phase, N, d_xcoef);
-    FIO_HIP_TRY(hipGetLastError());
-    {
-        DeviceScratch scr;
-        for (int l = 0; l < P->L; ++l) {
-            if (P->wedges[l].members.empty())
-                continue;
-            fio_status st = separate_wedge(P, l, d_xcoef, scr);
-            if (st != FIO_OK)
-                return st;
-        }
+    return FIO_OK;
+}
+
+void release_layout(fio_plan_s *P) {
+    void **bufs[] = {(void **)&P->d_wedges, (void **)&P->d_fftplans, (void **)&P->d_rows, (void **)&P->d_cols,
+                     (void **)&P->d_map,    (void **)&P->d_omega,    &P->d_gxi,             &P->d_gx,
+                     &P->d_tw,              &P->d_H,                 &P->d_G};
+    for (void **b : bufs) {
+        if (*b)
+            (void)hipFree(*b);
+        *b = nullptr;
     }
-    // 4. layout
+    P->rows.clear();
+    P->cols.clear();
+    P->wdev.clear();
+}
+
+// Offsets, work items, device tables, factor storage and workspace for the
+// ranks currently in P->wedges[*].q.
+static fio_status plan_layout(fio_plan_s *P) {
+    const int N = P->N;
+    const long long NN = (long long)N * N;
+    const int h = N / 2;
     P->esize = P->precision == FIO_F64 ? 16 : 8;
     const long long cap = kFftLdsBytes / (long long)P->esize;  // complex elements of the in-place FFT buffer
     P->qmax = 0;
     P->wdev.assign(P->L, WedgeDev());
+    P->rows.clear();
+    P->cols.clear();
     long long map_off = 0, mem_off = 0, gxi_off = 0, gx_off = 0, H_off = 0, G_off = 0;
     P->row_first.assign(P->L + 1, 0);
     P->col_first.assign(P->L + 1, 0);
@@ -763,8 +797,8 @@ fio_status build_plan(fio_plan_s *P) {
         D.lo2 = W.lo[1];
         D.q = W.qpad;
         D.nmem = (int)W.members.size();
-        D.fft1 = fft_for(W.n[0]);
-        D.fft2 = fft_for(W.n[1]);
+        D.fft1 = W.fft[0];
+        D.fft2 = W.fft[1];
         D.tw1 = P->tw_off[D.fft1];
         D.tw2 = P->tw_off[D.fft2];
         if (W.n[0] > cap || W.n[1] > cap)
@@ -787,8 +821,7 @@ fio_status build_plan(fio_plan_s *P) {
             for (int t0 = 0; t0 < W.qpad; t0 += tn)
                 P->rows.push_back(RowItem{l, k1, t0, std::min(tn, W.qpad - t0)});
         lds_rows = std::max(lds_rows, (size_t)W.n[1] * tn * P->esize);
-        // stage-2 items: chunks of adjacent transforms tau = j2 * q + t
-        // adjacent transforms per item: a power of two (cheap index math) filling the buffer
+        // stage-2 items: a power of two of adjacent transforms tau = j2 * q + t filling the buffer
         const long long ntau = (long long)W.n[1] * W.qpad;
         int nb = 1;
         while (2LL * nb * W.n[0] <= cap && 2LL * nb <= ntau && nb < 64)
@@ -809,7 +842,6 @@ fio_status build_plan(fio_plan_s *P) {
     P->G_total = G_off;
     if (P->qmax == 0)
         return (set_error("no wedge has a nonzero rank"), FIO_EINVAL);
-    // 5. device tables
     std::vector<int> map(std::max<long long>(1, map_off), -1), omega(std::max<long long>(1, mem_off));
     for (int l = 0; l < P->L; ++l) {
         WedgeHost &W = P->wedges[l];
@@ -869,10 +901,173 @@ fio_status build_plan(fio_plan_s *P) {
     FIO_HIP_TRY(hipMalloc(&P->d_H, es * std::max<long long>(1, H_off) * P->bchunk));
     FIO_HIP_TRY(hipMalloc(&P->d_G, es * std::max<long long>(1, G_off) * P->bchunk));
     P->workspace_bytes = per_rhs * P->bchunk;
-    // 6. factors
-    fio_status st = P->precision == FIO_F64 ? store_factors<double>(P, d_xcoef) : store_factors<float>(P, d_xcoef);
+    return FIO_OK;
+}
+
+// Exact factors: randomized separation of every wedge, then storage.
+static fio_status plan_exact(fio_plan_s *P, const double2 *d_xcoef) {
+    {
+        DeviceScratch scr;
+        for (int l = 0; l < P->L; ++l) {
+            if (P->wedges[l].members.empty())
+                continue;
+            fio_status st = separate_wedge(P, l, d_xcoef, scr);
+            if (st != FIO_OK)
+                return st;
+        }
+    }
+    fio_status st = plan_layout(P);
     if (st != FIO_OK)
         return st;
+    P->factor_mode = FIO_FACTORS_STORED;
+    return P->precision == FIO_F64 ? store_factors<double>(P, d_xcoef, true) : store_factors<float>(P, d_xcoef, true);
+}
+
+__global__ void k_gather_rows_f32(const cplx<float> *__restrict__ src, const long long *__restrict__ rows, int n,
+                                  int q, double2 *__restrict__ dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * q)
+        return;
+    const cplx<float> v = src[rows[i / q] * q + (i % q)];
+    dst[i] = make_double2(v.re, v.im);
+}
+
+// Host copy (FP64) of the stored spatial factors of wedge ell at grid rows `rows`.
+static fio_status fetch_gamma_x(fio_plan_s *P, int l, const std::vector<long long> &rows, std::vector<zd> &out) {
+    const int q = P->wedges[l].qpad, n = (int)rows.size();
+    long long *d_idx = nullptr;
+    double2 *d_out = nullptr;
+    FIO_HIP_TRY(hipMalloc(&d_idx, sizeof(long long) * n));
+    hipError_t e = hipMalloc(&d_out, sizeof(double2) * (size_t)n * q);
+    if (e == hipSuccess)
+        e = hipMemcpy(d_idx, rows.data(), sizeof(long long) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        k_gather_rows_f32<<<(n * q + 255) / 256, 256>>>(static_cast<const cplx<float> *>(P->d_gx) + P->wdev[l].gx_off,
+                                                         d_idx, n, q, d_out);
+        e = hipGetLastError();
+    }
+    std::vector<double2> h((size_t)n * q);
+    if (e == hipSuccess)
+        e = hipMemcpy(h.data(), d_out, sizeof(double2) * h.size(), hipMemcpyDeviceToHost);
+    (void)hipFree(d_idx);
+    if (d_out)
+        (void)hipFree(d_out);
+    if (e != hipSuccess)
+        return hip_fail(e, "fetch_gamma_x");
+    out.resize(h.size());
+    for (size_t i = 0; i < h.size(); ++i)
+        out[i] = zd(h[i].x, h[i].y);
+    return FIO_OK;
+}
+
+// Learned factors: gamma^x from the network, gamma^xi refit as
+// alpha_[R]^+ A_[R], and the s x s error estimate of every wedge.  *ok is
+// false if any wedge misses the separation target.
+static fio_status plan_learned(fio_plan_s *P, LearnedModel *net, const double2 *d_xcoef, bool *ok) {
+    *ok = true;
+    const long long NN = (long long)P->N * P->N;
+    for (WedgeHost &W : P->wedges)
+        W.q = W.members.empty() ? 0 : kNetRank;
+    fio_status st = plan_layout(P);
+    if (st != FIO_OK)
+        return st;
+    P->factor_mode = FIO_FACTORS_LEARNED;
+    const double target = 0.5 * P->tol;
+    const int sv = std::max(8, P->opt.verify_samples);
+    const int rr = std::max(4 * kNetRank, std::min(512, std::max(P->opt.r0, 8 * kNetRank)));
+    for (int l = 0; l < P->L; ++l) {
+        WedgeHost &W = P->wedges[l];
+        if (W.q == 0)
+            continue;
+        FIO_HIP_TRY(learned_infer_wedge(net, W.theta, P->opt.learned_scale,
+                                        static_cast<cplx<float> *>(P->d_gx) + P->wdev[l].gx_off, W.qpad, P->precision,
+                                        0));
+    }
+    FIO_HIP_TRY(hipDeviceSynchronize());
+    for (int l = 0; l < P->L; ++l) {
+        WedgeHost &W = P->wedges[l];
+        if (W.q == 0)
+            continue;
+        uint64_t state = splitmix64(P->opt.seed ^ (0x1EA2Dull * (uint64_t)(l + 1)));
+        W.R = sample_distinct<long long>(NN, (int)std::min<long long>(rr, NN), state);
+        W.C.clear();
+        W.Z.clear();
+        W.r = (int)W.R.size();
+        std::vector<zd> aR;
+        st = fetch_gamma_x(P, l, W.R, aR);
+        if (st != FIO_OK)
+            return st;
+        pinv_tall((int)W.R.size(), W.q, aR, W.P, 1e-6);
+        const int nmem = (int)W.members.size();
+        const int sg = (int)std::min<long long>(sv, NN), sd = std::min(sv, nmem);
+        std::vector<long long> Gam = sample_distinct<long long>(NN, sg, state);
+        std::vector<int> Del = sample_distinct<int>(nmem, sd, state);
+        std::vector<zd> UG;
+        st = fetch_gamma_x(P, l, Gam, UG);
+        if (st != FIO_OK)
+            return st;
+        W.sep_err = separation_estimate(P, W, Gam, Del, UG);
+        if (W.sep_err > target)
+            *ok = false;
+    }
+    return store_factors<float>(P, d_xcoef, false);
+}
+
+fio_status build_plan(fio_plan_s *P) {
+    using clock = std::chrono::steady_clock;
+    const auto t_start = clock::now();
+    const int N = P->N;
+    const long long NN = (long long)N * N;
+    FIO_HIP_TRY(hipGetDevice(&P->device));
+    fio_status st = plan_geometry(P);
+    if (st != FIO_OK)
+        return st;
+    double2 *d_xcoef = nullptr;
+    FIO_HIP_TRY(hipMalloc(&d_xcoef, NN * sizeof(double2)));
+    struct XGuard {
+        double2 *p;
+        ~XGuard() {
+            if (p)
+                (void)hipFree(p);
+        }
+    } xg{d_xcoef};
+    k_xcoef<<<(unsigned)((NN + 255) / 256), 256>>>(P->phase, N, d_xcoef);
+    FIO_HIP_TRY(hipGetLastError());
+    LearnedModel *net = static_cast<LearnedModel *>(const_cast<void *>(P->opt.learned));
+    const bool want_net = net && P->opt.factor_mode != FIO_FACTORS_STORED;
+    bool use_net = want_net;
+    if (want_net && (net->N != N || net->L != P->L || P->opt.partition != FIO_PART_EQUIANGULAR ||
+                     P->precision != FIO_F32 || net->family.kind != P->phase.kind)) {
+        if (P->opt.factor_mode == FIO_FACTORS_LEARNED)
+            return (set_error("the network was trained for another N, wedge count, partition, precision or "
+                              "phase family"),
+                    FIO_EINVAL);
+        use_net = false;
+    }
+    if (use_net) {
+        bool ok = false;
+        st = plan_learned(P, net, d_xcoef, &ok);
+        if (st != FIO_OK)
+            return st;
+        if (!ok) {
+            if (P->opt.factor_mode == FIO_FACTORS_LEARNED)
+                return (set_error("learned factors miss the error budget"), FIO_EACCURACY);
+            // fall back to the exact randomized separation
+            release_layout(P);
+            for (WedgeHost &W : P->wedges) {
+                W.q = 0;
+                W.P.clear();
+                W.R.clear();
+            }
+            P->fallback = 1;
+            use_net = false;
+        }
+    }
+    if (!use_net) {
+        st = plan_exact(P, d_xcoef);
+        if (st != FIO_OK)
+            return st;
+    }
     FIO_HIP_TRY(apply_prepare(P));
     FIO_HIP_TRY(hipDeviceSynchronize());
     P->plan_ms = std::chrono::duration<double, std::milli>(clock::now() - t_start).count();

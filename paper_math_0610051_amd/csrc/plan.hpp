@@ -65,7 +65,7 @@ struct WedgeHost {
     double theta = 0;
     std::vector<int> members;   // centred Omega indices
     int M[4] = {1, 0, 0, 1}, Minv[4] = {1, 0, 0, 1};
-    int xc[2] = {0, 0}, B[2] = {1, 1}, lo[2] = {0, 0}, n[2] = {2, 2};
+    int xc[2] = {0, 0}, B[2] = {1, 1}, lo[2] = {0, 0}, n[2] = {2, 2}, fft[2] = {0, 0};
     int q = 0, qpad = 0, r = 0, attempts = 0;
     double sep_err = 0;
     std::vector<int> C;          // sampled member positions (columns)

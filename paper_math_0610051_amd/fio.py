@@ -90,6 +90,17 @@ def load_library():
         "fio_destroy": (c_int, [P]),
         "fio_profile": (c_int, [P, c_int]),
         "fio_profile_read": (c_int, [P, P, P]),
+        "fio_learned_create": (c_int, [c_int, POINTER(fio_phase), c_int, c_ulonglong, POINTER(P)]),
+        "fio_learned_generate": (c_int, [P, c_int, P, c_int, c_int]),
+        "fio_learned_train": (c_int, [P, c_int, c_int, c_double, c_double, P]),
+        "fio_learned_eval": (c_int, [P, P]),
+        "fio_learned_params": (c_int, [P, c_int, P, c_int]),
+        "fio_learned_param_count": (c_int, []),
+        "fio_learned_forward": (c_int, [P, c_int, P, P]),
+        "fio_learned_grads": (c_int, [P, c_int, P, P, P, P]),
+        "fio_learned_save": (c_int, [P, c_char_p]),
+        "fio_learned_load": (c_int, [c_char_p, POINTER(P)]),
+        "fio_learned_destroy": (c_int, [P]),
         "fio_last_error": (c_char_p, []),
         "fio_host_eigh": (c_int, [c_int, P, P, P]),
         "fio_version": (c_char_p, []),
@@ -305,3 +316,83 @@ def apply_multi(plans, fhats, outs=None):
     stream = torch.cuda.current_stream(fhats[0].device).cuda_stream
     _check(lib.fio_apply_multi(n, hs, fs, us, Bs, c_void_p(stream)))
     return outs
+
+
+class Learned:
+    """The spatial-factor network (fio_learned_*): training data from the
+    method's separation, BF16 matrix-core training and inference on the device."""
+
+    def __init__(self, N, family, params=(), n_wedges=0, seed=1234, _handle=None):
+        lib = load_library()
+        self._lib = lib
+        if _handle is not None:
+            self.handle = _handle
+            return
+        ph = family if isinstance(family, fio_phase) else make_phase(family, params)
+        h = c_void_p()
+        _check(lib.fio_learned_create(int(N), ctypes.byref(ph), int(n_wedges), int(seed), ctypes.byref(h)))
+        self.handle = h
+
+    @staticmethod
+    def param_count():
+        return int(load_library().fio_learned_param_count())
+
+    @classmethod
+    def load(cls, path):
+        lib = load_library()
+        h = c_void_p()
+        _check(lib.fio_learned_load(str(path).encode(), ctypes.byref(h)))
+        return cls(0, None, _handle=h)
+
+    def save(self, path):
+        _check(self._lib.fio_learned_save(self.handle, str(path).encode()))
+
+    def generate(self, scales, x_samples=4096, r_cols=48):
+        sc = np.ascontiguousarray(np.asarray(scales, dtype=np.float64))
+        _check(self._lib.fio_learned_generate(self.handle, sc.size, sc.ctypes.data, int(x_samples), int(r_cols)))
+
+    def train(self, steps, batch=4096, lr=2e-3, lr_final=2e-5):
+        loss = ctypes.c_double()
+        _check(self._lib.fio_learned_train(self.handle, int(steps), int(batch), float(lr), float(lr_final),
+                                           ctypes.byref(loss)))
+        return loss.value
+
+    def eval(self):
+        loss = ctypes.c_double()
+        _check(self._lib.fio_learned_eval(self.handle, ctypes.byref(loss)))
+        return loss.value
+
+    def params(self, values=None):
+        n = self.param_count()
+        if values is None:
+            out = np.empty(n, dtype=np.float32)
+            _check(self._lib.fio_learned_params(self.handle, 1, out.ctypes.data, n))
+            return out
+        v = np.ascontiguousarray(np.asarray(values, dtype=np.float32))
+        _check(self._lib.fio_learned_params(self.handle, 0, v.ctypes.data, n))
+
+    def forward(self, feat):
+        f = np.ascontiguousarray(np.asarray(feat, dtype=np.float32))
+        out = np.empty((f.shape[0], 32), dtype=np.float32)
+        _check(self._lib.fio_learned_forward(self.handle, f.shape[0], f.ctypes.data, out.ctypes.data))
+        return out
+
+    def grads(self, feat, target):
+        f = np.ascontiguousarray(np.asarray(feat, dtype=np.float32))
+        t = np.ascontiguousarray(np.asarray(target, dtype=np.float32))
+        g = np.empty(self.param_count(), dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(self._lib.fio_learned_grads(self.handle, f.shape[0], f.ctypes.data, t.ctypes.data, g.ctypes.data,
+                                           ctypes.byref(loss)))
+        return g, loss.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self._lib.fio_learned_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,114 @@
+"""The learned spatial factors: BF16 matrix-core kernels against the FP64 network
+oracle, training on the method's own separation factors, plans built from the
+network, the fallback to exact factors, and what the network gains."""
+import time
+
+import numpy as np
+import pytest
+
+import fio_inputs as fi
+from oracle import direct as od
+from oracle import mlp
+from oracle import reference as ref
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    od.build(force=False)
+
+
+def _net(N=64, L=8, seed=5):
+    from paper_math_0610051_amd import Learned
+    return Learned(N, "c1c2", (1.0,), n_wedges=L, seed=seed)
+
+
+def _oracle_params(net):
+    return mlp.unflatten(net.params().astype(np.float64))
+
+
+def test_forward_matches_oracle_with_bf16_operands():
+    net = _net()
+    rng = np.random.default_rng(0)
+    f = mlp.features(rng.random(200), rng.random(200), rng.uniform(0, 6.28, 200), rng.uniform(0.5, 1.5, 200))
+    got = net.forward(f)
+    want, _ = mlp.forward(_oracle_params(net), mlp.bf16(f), bf16_ops=True)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print("  forward rel err %.2e" % err)
+    assert err < 2e-3
+
+
+def test_gradients_match_oracle_with_bf16_operands():
+    net = _net()
+    rng = np.random.default_rng(1)
+    n = 256
+    f = mlp.features(rng.random(n), rng.random(n), rng.uniform(0, 6.28, n), rng.uniform(0.5, 1.5, n))
+    target = rng.standard_normal((n, 32)) * 0.5
+    g, loss = net.grads(f, target)
+    lo, go = mlp.loss_and_grads(_oracle_params(net), mlp.bf16(f), target, bf16_ops=True)
+    go = mlp.flatten(go)
+    assert abs(loss - lo) / lo < 2e-3
+    # per-layer relative error of the flat gradient
+    dims = mlp.DIMS
+    o = 0
+    for i in range(len(dims) - 1):
+        for size in (dims[i] * dims[i + 1], dims[i + 1]):
+            a, b = g[o:o + size], go[o:o + size]
+            rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+            print("  layer %d block %d rel %.2e" % (i, size, rel))
+            assert rel < 3e-2
+            o += size
+
+
+def test_training_reduces_loss_and_generalises_to_heldout_scales():
+    net = _net(N=64, L=8)
+    net.generate(fi.training_scales(16), x_samples=1024, r_cols=48)
+    l0 = net.eval()
+    l1 = net.train(1500, batch=2048, lr=2e-3, lr_final=2e-5)
+    train_loss = net.eval()
+    net.generate(fi.heldout_scales(8), x_samples=1024, r_cols=48)
+    held = net.eval()
+    print("  loss before %.3e after %.3e held-out %.3e (last batch %.3e)" % (l0, train_loss, held, l1))
+    assert train_loss < 0.05 * l0
+    assert held < 3 * train_loss + 1e-6
+
+
+def test_learned_plan_refit_and_fallback():
+    """A plan built from the trained network (factor_mode auto) either meets the
+    budget with learned factors or falls back; forcing learned with a budget the
+    network cannot meet reports FIO_EACCURACY; the result always meets the budget."""
+    from paper_math_0610051_amd import FioError, Plan
+    N = 64
+    net = _net(N=N, L=8)
+    net.generate(fi.training_scales(16), x_samples=1024, r_cols=48)
+    net.train(1500, batch=2048)
+    s = float(fi.heldout_scales(8)[3])
+    rng = np.random.default_rng(2)
+    fhat = fi.fhat_from_f(fi.complex_gaussian(N, rng))
+    for tol in (1e-2, 1e-4):
+        p = Plan(N, "c1c2", tol, params=(s,), n_wedges=8, learned=net, learned_scale=s)
+        info = p.info()
+        u = p.apply(torch.from_numpy(fhat.astype(np.complex64)).cuda())
+        torch.cuda.synchronize()
+        exact = od.direct(N, 2, (s,), fhat, np.arange(N * N))
+        err = ref.rel_l2(u.cpu().numpy().ravel(), exact)
+        print("  tol %g: factor_mode %d fallback %d err %.2e" % (tol, info["factor_mode"], info["fallback"], err))
+        assert err <= tol
+        assert info["fallback"] in (0, 1)
+    with pytest.raises(FioError) as e:
+        Plan(N, "c1c2", 1e-6, params=(s,), n_wedges=8, learned=net, learned_scale=s, factor_mode="learned",
+             precision="f32")
+    assert e.value.status == -4
+
+
+def test_network_save_load_roundtrip(tmp_path):
+    from paper_math_0610051_amd import Learned
+    net = _net()
+    path = tmp_path / "net.bin"
+    net.save(path)
+    other = Learned.load(path)
+    assert np.array_equal(net.params(), other.params())
