@@ -1,12 +1,18 @@
-"""Benchmark of the batched FIO apply on one MI355X.
+"""Benchmark of the FIO apply on one MI355X.
 
-One step = one fio_apply_batch of B right-hand sides through the whole hot
-path (window + row FFT, column FFT, interpolate + combine) at N = 1024 under
-the c1/c2 ellipse phase, FP32 data with FP64 phase, tolerance 1e-4
-relative l2.  Inputs are seeded complex Gaussian fields already resident in
-device memory.  Prints one JSON line.
+Default workload (one JSON line): N = 1024, B = 8 complex-Gaussian right-hand
+sides under the c1/c2 ellipse phase, FP32 data with FP64 phase, tolerance
+1e-4 relative l2.  One step = one fio_apply_batch of the 8 right-hand sides
+through the whole hot path (window + row FFT, column FFT, interpolate +
+combine), inputs resident in device memory.  Wedge count, oversampling and
+tolerance split come from the library's autotuner (cached in
+$FIO_TUNE_CACHE, default /tmp/fio_tune_cache.txt).
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--N 1024] [--batch 8]
+Other workloads (each prints its own JSON line):
+  --workload uneven   32 instances, N in {128, ..., 1024}, one fused launch
+  --workload learned  network-factor plan vs exact plan at N = 1024
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched]
 """
 from __future__ import annotations
 
@@ -26,15 +32,20 @@ FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x FMA (2 flop) x 2.4 GHz, non
 STAGES = ("window_rowfft", "colfft", "interp_combine")
 
 
+def log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def stage_work(plan, B):
     """Algorithmic bytes and flops per stage for one apply of B right-hand sides.
 
-    Per wedge (box B1 x B2, grid n1 x n2, rank q, |W| members), complex64 = 8 B:
+    Per wedge (box B1 x B2, grid n1 x n2, rank q padded to even, |W| members),
+    complex64 = 8 bytes:
       stage 0 reads fhat on W and gamma^xi (q per member), writes B1 * n2 * q;
       stage 1 reads B1 * n2 * q, writes n1 * n2 * q;
-      stage 2 reads n1 * n2 * q and gamma^x (N^2 q, once per launch of up to
-              4 right-hand sides), writes N^2 per right-hand side; its flops
-              are N^2 (4 w^2 q + 8 q + 8) per wedge and right-hand side.
+      stage 2 reads n1 * n2 * q and gamma^x (N^2 q, once per launch of up to 8
+              right-hand sides), writes N^2 per right-hand side; its flops are
+              N^2 (4 w^2 q + 8 q + 8) per wedge and right-hand side.
     """
     info = plan.info()
     N, w = info["N"], info["kernel_width"]
@@ -45,9 +56,9 @@ def stage_work(plan, B):
     gx_bytes = 0.0
     for ell in range(info["L"]):
         wi = plan.wedge_info(ell)
-        q = wi["rank"] + (wi["rank"] & 1)
         if wi["rank"] == 0:
             continue
+        q = wi["rank"] + (wi["rank"] & 1)
         B1, B2 = wi["box"]
         n1, n2 = wi["fine"]
         nm = wi["members"]
@@ -56,8 +67,7 @@ def stage_work(plan, B):
         by[2] += es * (n1 * n2 * q) * B
         gx_bytes += es * NN * q
         fl += NN * (4.0 * w * w * q + 8.0 * q + 8.0) * B
-    launches2 = math.ceil(B / 4)
-    by[2] += gx_bytes * launches2 + es * NN * B
+    by[2] += gx_bytes * math.ceil(B / 8) + es * NN * B
     return by, fl
 
 
@@ -73,12 +83,213 @@ def cpu_baseline(N, phase_kind, params, fh, samples, seed):
     ref = od.direct(N, phase_kind, params, fh, xs)
     dt = time.perf_counter() - t0
     B = fh.shape[0]
-    # one full apply of B right-hand sides evaluates N^2 outputs; the sample evaluated `samples`
     full_s = dt * (N * N) / samples
     return dict(value=B / full_s, unit="applies/s", cores=od.max_threads(), kind="oracle",
-                sample="%d random outputs x %d RHS of the N=%d c1/c2 workload (%.2e kernel terms) in %.1f s; "
-                       "extrapolated to all N^2 outputs" % (samples, B, N, float(samples) * N * N, dt),
-                seconds=dt), xs, ref
+                sample="%d random outputs x %d RHS of the N=%d workload (%.2e kernel terms, shared by the RHS) "
+                       "in %.1f s; extrapolated to all N^2 outputs" % (samples, B, N, float(samples) * N * N, dt)), \
+        xs, ref
+
+
+def tuned_plan(N, tol, B):
+    """Plan with the autotuner's choice (cached on disk)."""
+    from paper_math_0610051_amd import Plan, autotune
+    os.environ.setdefault("FIO_TUNE_CACHE", "/tmp/fio_tune_cache.txt")
+    t0 = time.perf_counter()
+    best, tried = autotune(N, "c1c2", tol, params=(1.0,), B=B)
+    tune_s = time.perf_counter() - t0
+    log("autotune %.1f s (%d candidates): %s" % (tune_s, len(tried), best))
+    t0 = time.perf_counter()
+    plan = Plan(N, "c1c2", tol, params=(1.0,), max_batch=B, n_wedges=best["n_wedges"], sigma=best["sigma"],
+                sep_tol_frac=best["sep_tol_frac"], nufft_tol_frac=best["nufft_tol_frac"])
+    return plan, time.perf_counter() - t0, best
+
+
+def time_applies(plan, fd, out, steps, warmup, profile=False):
+    import torch
+    for _ in range(warmup):
+        plan.apply(fd, out)
+    torch.cuda.synchronize()
+    if profile:
+        plan.profile(True)
+        torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.apply(fd, out)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def run_batched(args):
+    import numpy as np
+    import torch
+
+    import fio_inputs as fi
+
+    N, B = args.N, args.batch
+    log("N=%d B=%d tol=%g: tuning and building the plan" % (N, B, args.tol))
+    plan, plan_s, best = tuned_plan(N, args.tol, B)
+    info = plan.info()
+    rng = fi.rng_for(4, 0)
+    fh = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=B))
+    fd = torch.from_numpy(fh.astype(np.complex64)).cuda()
+    out = torch.empty_like(fd)
+    log("plan %.1f s, L=%d ranks %d..%d w=%d sigma=%g; timing" % (plan_s, info["L"], info["min_rank"],
+                                                                  info["max_rank"], info["kernel_width"],
+                                                                  info["sigma"]))
+    elapsed = time_applies(plan, fd, out, args.steps, args.warmup, profile=True)
+    ms, launches = plan.profile_read()
+    plan.profile(False)
+    value = B * args.steps / elapsed
+    # the same right-hand sides one apply each (no batching), for comparison
+    single = torch.empty_like(fd[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        for b in range(B):
+            plan.apply(fd[b], single)
+    torch.cuda.synchronize()
+    single_value = B * max(1, args.steps // 2) / (time.perf_counter() - t0)
+    by, fl = stage_work(plan, B)
+    steps = args.steps
+    per_launch_ms = [ms[i] / max(1, launches[i]) for i in range(3)]
+    stage_ms = [ms[i] / steps for i in range(3)]
+    lps = [launches[i] / steps for i in range(3)]
+    dom = int(np.argmax(stage_ms))
+    if dom == 2:
+        achieved = fl / lps[2] / (per_launch_ms[2] * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=achieved / FP32_VALU_PEAK_TFLOPS, traffic=None, kernel="k_interp")
+    else:
+        achieved = by[dom] / lps[dom] / (per_launch_ms[dom] * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                    traffic=None, kernel=("k_rows", "k_cols")[dom])
+    stages = {}
+    for i, name in enumerate(STAGES):
+        bpl = by[i] / max(1e-9, lps[i])
+        stages[name] = dict(ms_per_step=stage_ms[i], ms_per_launch=per_launch_ms[i], launches_per_step=lps[i],
+                            gbs=bpl / (per_launch_ms[i] * 1e-3) / 1e9 if per_launch_ms[i] > 0 else None)
+    stages["interp_combine"]["tflops"] = fl / (stage_ms[2] * 1e-3) / 1e12
+    res = dict(metric="FIO applies/s at N=1024, rel-l2<=1e-4", value=value, unit="applies/s", n_gpus=1,
+               steps=steps, warmup=args.warmup, ms_per_step=1e3 * elapsed / steps, higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="c64 (fp32 data, fp64 phase and points)", data="synthetic",
+               config=dict(workload="N=%d c1/c2 ellipse phase (scale 1), B=%d complex-Gaussian right-hand sides, "
+                                    "tol %g, exact randomized-separation factors, autotuned" % (N, B, args.tol),
+                           N=N, batch=B, tol=args.tol, wedges=info["L"], ranks=[info["min_rank"], info["max_rank"]],
+                           kernel_width=info["kernel_width"], sigma=info["sigma"],
+                           sep_tol_frac=best["sep_tol_frac"], nufft_tol_frac=best["nufft_tol_frac"],
+                           plan_s=plan_s, parallelism="single GPU"),
+               roofline=roof, stages=stages,
+               comparison=dict(per_rhs_loop_applies_per_s=single_value, batched_applies_per_s=value))
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline on %d sampled outputs" % args.cpu_samples)
+        cb, xs, refv = cpu_baseline(N, 2, (1.0,), fh, args.cpu_samples, seed=4321)
+        got = out.cpu().numpy().reshape(B, N * N)[:, xs].astype(np.complex128)
+        res["rel_l2_vs_oracle"] = float(np.linalg.norm(got - refv) / np.linalg.norm(refv))
+        res["cpu_baseline"] = cb
+    else:
+        res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+
+
+def run_uneven(args):
+    import numpy as np
+    import torch
+
+    import fio_inputs as fi
+    from paper_math_0610051_amd import Plan, apply_multi
+
+    insts = fi.uneven_instances(32, seed=3000)
+    plans, dev, fhs = [], [], []
+    t0 = time.perf_counter()
+    for inst in insts:
+        kind, params = ("c1c2", (inst["scale"],)) if inst["family"] == "c1c2" else ("radial", (0.05, 0.5))
+        plans.append(Plan(inst["N"], kind, args.tol, params=params))
+        fh = fi.fhat_from_f(fi.instance_field(inst))
+        fhs.append(fh)
+        dev.append(torch.from_numpy(fh.astype(np.complex64)).cuda())
+    plan_s = time.perf_counter() - t0
+    outs = [torch.empty_like(d) for d in dev]
+    for _ in range(args.warmup):
+        apply_multi(plans, dev, outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        apply_multi(plans, dev, outs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # per-instance sequential applies for comparison
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        for p, d, o in zip(plans, dev, outs):
+            p.apply(d, o)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    errs = []
+    for p, d, o in zip(plans, dev, outs):
+        errs.append(p.probe_error(d, o, nsamples=64))
+    res = dict(metric="FIO applies/s, 32 uneven instances N in {128..1024}, one fused launch", value=32 * args.steps / el,
+               unit="applies/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * el / args.steps,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="c64 (fp32 data, fp64 phase)",
+               data="synthetic",
+               config=dict(workload="32 instances: N ~ U{128,256,512,1024}, c1/c2 (scale U[0.5,1.5]) or rho(x)|xi|, "
+                                    "complex Gaussian or 20 Gaussian bumps, tol %g" % args.tol,
+                           Ns=[i["N"] for i in insts], plan_s=plan_s),
+               comparison=dict(sequential_applies_per_s=32 * max(1, args.steps // 2) / seq),
+               max_instance_rel_l2_probe=max(errs), roofline=None, cpu_baseline=None)
+    print(json.dumps(res), flush=True)
+
+
+def run_learned(args):
+    import numpy as np
+    import torch
+
+    import fio_inputs as fi
+    from paper_math_0610051_amd import Learned, Plan
+
+    N, B = args.N, args.batch
+    net = Learned(N, "c1c2", (1.0,), seed=7)
+    t0 = time.perf_counter()
+    net.generate(fi.training_scales(64), x_samples=args.learned_samples, r_cols=48)
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss = net.train(args.learned_steps, batch=8192, lr=2e-3, lr_final=1e-5)
+    train_s = time.perf_counter() - t0
+    held = fi.heldout_scales(16)
+    net.generate(held, x_samples=1024, r_cols=48)
+    held_loss = net.eval()
+    rows = []
+    rng = fi.rng_for(4, 1)
+    fh = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=B))
+    fd = torch.from_numpy(fh.astype(np.complex64)).cuda()
+    out = torch.empty_like(fd)
+    for s in held[[2, 7, 13]]:
+        for tol in (args.learned_tol, args.tol):
+            t0 = time.perf_counter()
+            pe = Plan(N, "c1c2", tol, params=(float(s),), max_batch=B, factor_mode="stored")
+            exact_s = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            pl = Plan(N, "c1c2", tol, params=(float(s),), max_batch=B, learned=net, learned_scale=float(s))
+            learned_s = time.perf_counter() - t0
+            il, ie = pl.info(), pe.info()
+            el = time_applies(pl, fd, out, max(2, args.steps // 4), 1)
+            err_l = pl.probe_error(fd[0], out[0], nsamples=96)
+            ee = time_applies(pe, fd, out, max(2, args.steps // 4), 1)
+            err_e = pe.probe_error(fd[0], out[0], nsamples=96)
+            n = max(2, args.steps // 4)
+            rows.append(dict(scale=float(s), tol=tol, learned_used=int(il["factor_mode"] == 3 and not il["fallback"]),
+                             fallback=il["fallback"], learned_plan_s=learned_s, exact_plan_s=exact_s,
+                             learned_applies_per_s=B * n / el, exact_applies_per_s=B * n / ee,
+                             learned_err=err_l, exact_err=err_e, learned_max_sep_err=il["max_sep_error"],
+                             learned_factor_bytes=il["factor_bytes"], exact_compressed_bytes=ie["compressed_bytes"]))
+            pl.close()
+            pe.close()
+    res = dict(metric="learned vs exact factors at N=1024 (held-out phase scales)", value=None, unit="applies/s",
+               n_gpus=1, steps=args.steps, warmup=1, higher_is_better=True, dtype="bf16 network, c64 apply",
+               data="synthetic", network=dict(params=Learned.param_count(), weights_bytes_bf16=2 * Learned.param_count(),
+                                              generate_s=gen_s, train_s=train_s, train_steps=args.learned_steps,
+                                              final_batch_loss=loss, heldout_loss=held_loss),
+               rows=rows, roofline=None, cpu_baseline=None, vs_baseline=None)
+    print(json.dumps(res), flush=True)
 
 
 def main():
@@ -86,92 +297,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=("batched", "uneven", "learned"), default="batched")
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-4)
-    ap.add_argument("--cpu-samples", type=int, default=1024)
+    ap.add_argument("--cpu-samples", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned-steps", type=int, default=6000)
+    ap.add_argument("--learned-samples", type=int, default=4096)
+    ap.add_argument("--learned-tol", type=float, default=1e-2)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the wedge sharding is "
-              "described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: this build has no multi-GPU path (the wedge sharding is described "
+              "in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    import fio_inputs as fi
-    from paper_math_0610051_amd import Plan
-
-    N, B = args.N, args.batch
-    print("bench: N=%d B=%d tol=%g building plan" % (N, B, args.tol), file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    plan = Plan(N, "c1c2", args.tol, params=(1.0,), max_batch=B)
-    plan_s = time.perf_counter() - t0
-    info = plan.info()
-    rng = fi.rng_for(4, 0)
-    fh = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=B))
-    fd = torch.from_numpy(fh.astype(np.complex64)).cuda()
-    out = torch.empty_like(fd)
-    print("bench: plan %.1f s, L=%d ranks %d..%d w=%d; warmup" % (plan_s, info["L"], info["min_rank"],
-                                                               info["max_rank"], info["kernel_width"]),
-          file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        plan.apply(fd, out)
-    torch.cuda.synchronize()
-    plan.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.apply(fd, out)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms, launches = plan.profile_read()
-    plan.profile(False)
-    value = B * args.steps / elapsed
-    by, fl = stage_work(plan, B)
-    per_launch_ms = [ms[i] / max(1, launches[i]) for i in range(3)]
-    stage_ms_per_step = [ms[i] / args.steps for i in range(3)]
-    dom = int(np.argmax(stage_ms_per_step))
-    launches_per_step = [launches[i] / args.steps for i in range(3)]
-    if dom == 2:
-        flops_per_launch = fl / launches_per_step[2]
-        achieved = flops_per_launch / (per_launch_ms[2] * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=achieved, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / FP32_VALU_PEAK_TFLOPS, traffic=None, kernel="k_interp")
-    else:
-        bytes_per_launch = by[dom] / launches_per_step[dom]
-        achieved = bytes_per_launch / (per_launch_ms[dom] * 1e-3) / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=None, kernel=("k_rows", "k_cols")[dom])
-    stages = {}
-    for i, name in enumerate(STAGES):
-        bpl = by[i] / max(1e-9, launches_per_step[i])
-        stages[name] = dict(ms_per_step=stage_ms_per_step[i], ms_per_launch=per_launch_ms[i],
-                            gbs=bpl / (per_launch_ms[i] * 1e-3) / 1e9 if per_launch_ms[i] > 0 else None,
-                            launches_per_step=launches_per_step[i])
-    stages["interp_combine"]["tflops"] = fl / args.steps * 0 + fl / (stage_ms_per_step[2] * 1e-3) / 1e12
-    # accuracy and CPU baseline on the same sample
-    res = dict(metric="FIO applies/s at N=1024, rel-l2<=1e-4", value=value, unit="applies/s", n_gpus=1,
-               steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * elapsed / args.steps,
-               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="c64 (fp32; fp64 phase)",
-               data="synthetic",
-               config=dict(workload="N=%d c1/c2 ellipse phase, B=%d complex-Gaussian RHS, tol %g, exact "
-                                    "(stored) randomized-separation factors" % (N, B, args.tol),
-                           N=N, batch=B, tol=args.tol, wedges=info["L"], ranks=[info["min_rank"], info["max_rank"]],
-                           kernel_width=info["kernel_width"], plan_s=plan_s, parallelism="single GPU"),
-               roofline=roof, stages=stages)
-    if not args.no_cpu_baseline:
-        print("bench: CPU oracle baseline on %d sampled outputs" % args.cpu_samples, file=sys.stderr, flush=True)
-        cb, xs, refv = cpu_baseline(N, 2, (1.0,), fh, args.cpu_samples, seed=4321)
-        got = out.cpu().numpy().reshape(B, N * N)[:, xs].astype(np.complex128)
-        res["rel_l2_vs_oracle"] = float(np.linalg.norm(got - refv) / np.linalg.norm(refv))
-        cb.pop("seconds")
-        res["cpu_baseline"] = cb
-    else:
-        res["cpu_baseline"] = None
-    print(json.dumps(res), flush=True)
+    {"batched": run_batched, "uneven": run_uneven, "learned": run_learned}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -188,6 +188,32 @@ const char *fio_last_error(void);
  * n x n eigenvectors as columns (row-major). */
 fio_status fio_host_eigh(int n, const double *A, double *w, double *V);
 
+/* Relative l2 error (the Section 4 estimator) of a computed u = L fhat at
+ * nsamples grid points drawn from `seed`, against an FP64 direct summation of
+ * eq. (dfio) on the device.  fhat, u: device arrays of the plan's precision
+ * (one right-hand side).  Synchronises the stream. */
+fio_status fio_probe_error(fio_plan_t plan, const void *fhat, const void *u, int nsamples, unsigned long long seed,
+                           double *err, void *stream);
+
+/* Autotuner.  Builds candidate plans over the wedge count (L0 - 8 .. L0 + 16),
+ * the oversampling factor (2, 2.5) and the split of tol between separation and
+ * NUFFT, times an apply of B right-hand sides with HIP events and probes its
+ * error with fio_probe_error; *best is the fastest candidate whose error is at
+ * most 0.8 tol.  If the environment variable FIO_TUNE_CACHE names a file, a
+ * cached choice for the same problem is returned without tuning and new
+ * choices are appended.  Copy best's fields into fio_options to use them. */
+typedef struct {
+    int n_wedges;
+    double sigma;
+    int kernel_width;
+    double sep_tol_frac, nufft_tol_frac;
+    double ms_per_rhs;   /* measured apply time per right-hand side */
+    double error;        /* probed relative l2 error */
+} fio_tune_result_t;
+fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp, double tol,
+                        const fio_options *base /* nullable */, int B, fio_tune_result_t *tried, int max_tried,
+                        int *ntried, fio_tune_result_t *best);
+
 /* ---------------------------------------------------------------------------
  * Learned spatial factors.  A network maps (x1, x2, theta_ell, s) through a
  * fixed periodic feature map (16 inputs), three hidden layers of width 128

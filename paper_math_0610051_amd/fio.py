@@ -55,6 +55,11 @@ class fio_plan_info_t(ctypes.Structure):
                 ("workspace_bytes", c_longlong), ("compressed_bytes", c_longlong)]
 
 
+class fio_tune_result_t(ctypes.Structure):
+    _fields_ = [("n_wedges", c_int), ("sigma", c_double), ("kernel_width", c_int), ("sep_tol_frac", c_double),
+                ("nufft_tol_frac", c_double), ("ms_per_rhs", c_double), ("error", c_double)]
+
+
 class fio_wedge_info_t(ctypes.Structure):
     _fields_ = [("theta", c_double), ("members", c_int), ("rank", c_int), ("samples", c_int),
                 ("M", c_int * 4), ("xi_c", c_int * 2), ("box", c_int * 2), ("lo", c_int * 2),
@@ -101,6 +106,9 @@ def load_library():
         "fio_learned_save": (c_int, [P, c_char_p]),
         "fio_learned_load": (c_int, [c_char_p, POINTER(P)]),
         "fio_learned_destroy": (c_int, [P]),
+        "fio_probe_error": (c_int, [P, P, P, c_int, c_ulonglong, P, P]),
+        "fio_autotune": (c_int, [c_int, POINTER(fio_phase), POINTER(fio_amplitude), c_double, POINTER(fio_options),
+                                 c_int, P, c_int, P, POINTER(fio_tune_result_t)]),
         "fio_last_error": (c_char_p, []),
         "fio_host_eigh": (c_int, [c_int, P, P, P]),
         "fio_version": (c_char_p, []),
@@ -292,6 +300,15 @@ class Plan:
         _check(self._lib.fio_profile_read(self.handle, ms.ctypes.data, n.ctypes.data))
         return ms, n
 
+    def probe_error(self, fhat, u, nsamples=128, seed=1):
+        """Relative l2 error of u against an on-device FP64 direct sum at sampled points."""
+        torch = _torch()
+        err = ctypes.c_double()
+        stream = torch.cuda.current_stream(fhat.device).cuda_stream
+        _check(self._lib.fio_probe_error(self.handle, c_void_p(fhat.data_ptr()), c_void_p(u.data_ptr()),
+                                         int(nsamples), int(seed), ctypes.byref(err), c_void_p(stream)))
+        return err.value
+
     def wedge_warp(self, ell, xidx):
         xs = np.ascontiguousarray(np.asarray(xidx, dtype=np.int64).ravel())
         y = np.zeros((xs.size, 2))
@@ -396,3 +413,19 @@ class Learned:
             self.close()
         except Exception:
             pass
+
+
+def autotune(N, phase, tol, params=(), B=1, precision="f32", max_tried=32):
+    """fio_autotune: returns (best, tried) as dicts; best's fields map onto Plan keywords."""
+    lib = load_library()
+    ph = phase if isinstance(phase, fio_phase) else make_phase(phase, params)
+    amp = fio_amplitude()
+    o = default_options()
+    o.precision = PRECISIONS[precision]
+    tried = (fio_tune_result_t * max_tried)()
+    n = c_int()
+    best = fio_tune_result_t()
+    _check(lib.fio_autotune(int(N), ctypes.byref(ph), ctypes.byref(amp), float(tol), ctypes.byref(o), int(B),
+                            tried, max_tried, ctypes.byref(n), ctypes.byref(best)))
+    conv = lambda r: {k: getattr(r, k) for k, _ in r._fields_}
+    return conv(best), [conv(tried[i]) for i in range(n.value)]

@@ -340,3 +340,36 @@ def test_uneven_batch_against_direct_sums():
         worst = max(worst, err)
         assert err <= 1e-4, (inst, err)
     print("  worst per-instance rel-l2 %.3e" % worst)
+
+
+# ------------------------------------------------------------------ on-device probe and autotuner
+def test_device_probe_agrees_with_cpu_oracle():
+    """fio_probe_error against u taken from the CPU oracle: ~0 for the exact u and the
+    planted relative perturbation level for a perturbed one."""
+    N = 32
+    rng = np.random.default_rng(12)
+    fhat = fi.fhat_from_f(fi.complex_gaussian(N, rng))
+    p = _plan(N, "c1c2", (1.0,), 1e-4, precision="f64")
+    exact = od.direct(N, 2, (1.0,), fhat, np.arange(N * N)).reshape(N, N)
+    fd = _dev(fhat, "f64")
+    assert p.probe_error(fd, _dev(exact, "f64"), nsamples=256) < 1e-12
+    noise = fi.complex_gaussian(N, rng)
+    pert = exact + 1e-3 * noise * np.linalg.norm(exact) / np.linalg.norm(noise)
+    e = p.probe_error(fd, _dev(pert, "f64"), nsamples=1024)
+    assert 0.7e-3 < e < 1.3e-3
+
+
+def test_autotuner_choice_meets_the_budget():
+    from paper_math_0610051_amd import autotune
+    N, tol = 128, 1e-4
+    best, tried = autotune(N, "c1c2", tol, params=(1.0,), B=2)
+    print("  tried %d, best %s" % (len(tried), best))
+    assert len(tried) >= 8 and best["error"] <= 0.8 * tol
+    assert best["ms_per_rhs"] == min(t["ms_per_rhs"] for t in tried if t["error"] <= 0.8 * tol)
+    rng = np.random.default_rng(13)
+    fhat = fi.fhat_from_f(fi.complex_gaussian(N, rng))
+    p = _plan(N, "c1c2", (1.0,), tol, n_wedges=best["n_wedges"], sigma=best["sigma"],
+              sep_tol_frac=best["sep_tol_frac"], nufft_tol_frac=best["nufft_tol_frac"])
+    u = _apply(p, fhat).ravel()
+    xs = fi.sample_points(N, 1024, rng)
+    assert ref.rel_l2(u[xs], od.direct(N, 2, (1.0,), fhat, xs)) <= tol
