@@ -32,6 +32,9 @@ FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x FMA (2 flop) x 2.4 GHz, non
 STAGES = ("window_rowfft", "colfft", "interp_combine")
 
 
+from paper_math_0610051_amd import pmc  # noqa: E402
+
+
 def log(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
@@ -90,18 +93,42 @@ def cpu_baseline(N, phase_kind, params, fh, samples, seed):
         xs, ref
 
 
-def tuned_plan(N, tol, B):
-    """Plan with the autotuner's choice (cached on disk)."""
+def tuned_plan(N, tol, B, fixed=None):
+    """Plan with the autotuner's choice (cached on disk), or with fixed
+    (n_wedges, sigma, sep_tol_frac, nufft_tol_frac) when given."""
     from paper_math_0610051_amd import Plan, autotune
-    os.environ.setdefault("FIO_TUNE_CACHE", "/tmp/fio_tune_cache.txt")
-    t0 = time.perf_counter()
-    best, tried = autotune(N, "c1c2", tol, params=(1.0,), B=B)
-    tune_s = time.perf_counter() - t0
-    log("autotune %.1f s (%d candidates): %s" % (tune_s, len(tried), best))
+    if fixed is None:
+        os.environ.setdefault("FIO_TUNE_CACHE", "/tmp/fio_tune_cache.txt")
+        t0 = time.perf_counter()
+        best, tried = autotune(N, "c1c2", tol, params=(1.0,), B=B)
+        log("autotune %.1f s (%d candidates): %s" % (time.perf_counter() - t0, len(tried), best))
+    else:
+        L, sg, st, nt = fixed
+        best = dict(n_wedges=int(L), sigma=float(sg), sep_tol_frac=float(st), nufft_tol_frac=float(nt))
     t0 = time.perf_counter()
     plan = Plan(N, "c1c2", tol, params=(1.0,), max_batch=B, n_wedges=best["n_wedges"], sigma=best["sigma"],
                 sep_tol_frac=best["sep_tol_frac"], nufft_tol_frac=best["nufft_tol_frac"])
     return plan, time.perf_counter() - t0, best
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth: read + write bytes of fio_copy per second."""
+    import torch
+    from paper_math_0610051_amd import copy
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    for _ in range(3):
+        copy(a, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        copy(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ok = bool(torch.equal(a, b))
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9, ok
 
 
 def time_applies(plan, fd, out, steps, warmup, profile=False):
@@ -126,8 +153,13 @@ def run_batched(args):
     import fio_inputs as fi
 
     N, B = args.N, args.batch
-    log("N=%d B=%d tol=%g: tuning and building the plan" % (N, B, args.tol))
-    plan, plan_s, best = tuned_plan(N, args.tol, B)
+    copy_gbs, copy_ok = copy_bandwidth()
+    if not copy_ok:
+        raise SystemExit("fio_copy produced a wrong copy")
+    log("fio_copy: %.0f GB/s (read + write)" % copy_gbs)
+    log("N=%d B=%d tol=%g: planning" % (N, B, args.tol))
+    fixed = tuple(float(v) for v in args.plan_params.split(",")) if args.plan_params else None
+    plan, plan_s, best = tuned_plan(N, args.tol, B, fixed)
     info = plan.info()
     rng = fi.rng_for(4, 0)
     fh = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=B))
@@ -141,28 +173,38 @@ def run_batched(args):
     plan.profile(False)
     value = B * args.steps / elapsed
     # the same right-hand sides one apply each (no batching), for comparison
-    single = torch.empty_like(fd[0])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(max(1, args.steps // 2)):
-        for b in range(B):
-            plan.apply(fd[b], single)
-    torch.cuda.synchronize()
-    single_value = B * max(1, args.steps // 2) / (time.perf_counter() - t0)
+    single_value = None
+    if not args.no_compare:
+        single = torch.empty_like(fd[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, args.steps // 2)):
+            for b in range(B):
+                plan.apply(fd[b], single)
+        torch.cuda.synchronize()
+        single_value = B * max(1, args.steps // 2) / (time.perf_counter() - t0)
     by, fl = stage_work(plan, B)
     steps = args.steps
     per_launch_ms = [ms[i] / max(1, launches[i]) for i in range(3)]
     stage_ms = [ms[i] / steps for i in range(3)]
     lps = [launches[i] / steps for i in range(3)]
     dom = int(np.argmax(stage_ms))
+    kname = ("k_rows", "k_cols", "k_interp")[dom]
+    rec = pmc.load_traffic(args.traffic_record, kname, N=N, B=B, L=info["L"], sigma=info["sigma"],
+                           kernel_width=info["kernel_width"], ranks=[info["min_rank"], info["max_rank"]])
+    traffic = rec["traffic_bytes"] if rec else None
+    alg_bytes = by[dom] / lps[dom]
     if dom == 2:
         achieved = fl / lps[2] / (per_launch_ms[2] * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / FP32_VALU_PEAK_TFLOPS, traffic=None, kernel="k_interp")
+                    frac=achieved / FP32_VALU_PEAK_TFLOPS, traffic=traffic, kernel=kname)
     else:
-        achieved = by[dom] / lps[dom] / (per_launch_ms[dom] * 1e-3) / 1e9
+        achieved = alg_bytes / (per_launch_ms[dom] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=None, kernel=("k_rows", "k_cols")[dom])
+                    traffic=traffic, kernel=kname)
+    roof.update(algorithmic_bytes=alg_bytes, ms_per_launch=per_launch_ms[dom],
+                traffic_unit="HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                hbm_copy_gbs=copy_gbs)
     stages = {}
     for i, name in enumerate(STAGES):
         bpl = by[i] / max(1e-9, lps[i])
@@ -173,11 +215,11 @@ def run_batched(args):
                steps=steps, warmup=args.warmup, ms_per_step=1e3 * elapsed / steps, higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="c64 (fp32 data, fp64 phase and points)", data="synthetic",
                config=dict(workload="N=%d c1/c2 ellipse phase (scale 1), B=%d complex-Gaussian right-hand sides, "
-                                    "tol %g, exact randomized-separation factors, autotuned" % (N, B, args.tol),
+                                    "tol %g, exact randomized-separation factors, %s" % (N, B, args.tol, "autotuned" if fixed is None else "fixed plan"),
                            N=N, batch=B, tol=args.tol, wedges=info["L"], ranks=[info["min_rank"], info["max_rank"]],
                            kernel_width=info["kernel_width"], sigma=info["sigma"],
                            sep_tol_frac=best["sep_tol_frac"], nufft_tol_frac=best["nufft_tol_frac"],
-                           plan_s=plan_s, parallelism="single GPU"),
+                           plan_s=plan_s, tuned=fixed is None, parallelism="single GPU"),
                roofline=roof, stages=stages,
                comparison=dict(per_rhs_loop_applies_per_s=single_value, batched_applies_per_s=value))
     if not args.no_cpu_baseline:
@@ -303,6 +345,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--cpu-samples", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the per-RHS loop comparison")
+    ap.add_argument("--plan-params", default="", help="L,sigma,sep_tol_frac,nufft_tol_frac instead of autotuning")
+    ap.add_argument("--traffic-record", default=os.path.join(ROOT, "profiles", "k_interp_traffic_N1024_B8_c1c2.json"))
     ap.add_argument("--learned-steps", type=int, default=6000)
     ap.add_argument("--learned-samples", type=int, default=4096)
     ap.add_argument("--learned-tol", type=float, default=1e-2)

@@ -38,6 +38,8 @@
 #ifndef FIO_H
 #define FIO_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -194,6 +196,13 @@ fio_status fio_host_eigh(int n, const double *A, double *w, double *V);
  * (one right-hand side).  Synchronises the stream. */
 fio_status fio_probe_error(fio_plan_t plan, const void *fhat, const void *u, int nsamples, unsigned long long seed,
                            double *err, void *stream);
+
+/* Plain device-to-device copy of `bytes` (a multiple of 16; both pointers
+ * 16-byte aligned, device memory, non-overlapping) as one kernel launch on
+ * `stream`, asynchronous.  It is a measurement aid: its event time gives the
+ * achievable HBM bandwidth and its hardware byte counters calibrate those of
+ * the apply kernels.  FIO_EINVAL on a null or misaligned argument. */
+fio_status fio_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Autotuner.  Builds candidate plans over the wedge count (L0 - 8 .. L0 + 16),
  * the oversampling factor (2, 2.5) and the split of tol between separation and

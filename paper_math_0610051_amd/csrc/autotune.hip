@@ -6,8 +6,12 @@
 // plans over the wedge count, the oversampling factor and the split of the
 // tolerance between separation and NUFFT, times a batched apply with HIP
 // events, probes its accuracy, and keeps the fastest candidate within the
-// budget; choices are cached in a text file keyed by the problem.
+// budget; choices are cached in a text file keyed by the problem.  fio_copy
+// is a plain streaming copy whose hardware counters and event time calibrate
+// the traffic and bandwidth figures of the other kernels.
+#include <algorithm>
 #include <chrono>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -178,6 +182,14 @@ static void cache_store(const char *path, const std::string &key, const fio_tune
     std::fclose(f);
 }
 
+// Grid-stride copy of n 16-byte units; each lane moves one unit per iteration
+// so consecutive lanes touch consecutive addresses.
+__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] = src[i];
+}
+
 }  // namespace fio
 
 using namespace fio;
@@ -190,6 +202,20 @@ fio_status fio_probe_error(fio_plan_t plan, const void *fhat, const void *u, int
     if (!plan || !fhat || !u || !err || nsamples < 1)
         return (set_error("bad argument"), FIO_EINVAL);
     return probe_error(plan, fhat, u, nsamples, seed, err, static_cast<hipStream_t>(stream));
+}
+
+fio_status fio_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    set_error("");
+    if (!src || !dst || (bytes & 15) || ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15))
+        return (set_error("fio_copy needs non-null 16-byte aligned pointers and a multiple of 16 bytes"), FIO_EINVAL);
+    const size_t n = bytes / 16;
+    if (n == 0)
+        return FIO_OK;
+    const unsigned grid = (unsigned)std::min<size_t>((n + 255) / 256, 256 * 32);
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const uint4 *>(src), static_cast<uint4 *>(dst), n);
+    FIO_HIP_TRY(hipGetLastError());
+    return FIO_OK;
 }
 
 fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp, double tol, const fio_options *base,

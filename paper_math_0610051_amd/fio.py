@@ -107,6 +107,7 @@ def load_library():
         "fio_learned_load": (c_int, [c_char_p, POINTER(P)]),
         "fio_learned_destroy": (c_int, [P]),
         "fio_probe_error": (c_int, [P, P, P, c_int, c_ulonglong, P, P]),
+        "fio_copy": (c_int, [P, P, ctypes.c_size_t, P]),
         "fio_autotune": (c_int, [c_int, POINTER(fio_phase), POINTER(fio_amplitude), c_double, POINTER(fio_options),
                                  c_int, P, c_int, P, POINTER(fio_tune_result_t)]),
         "fio_last_error": (c_char_p, []),
@@ -413,6 +414,17 @@ class Learned:
             self.close()
         except Exception:
             pass
+
+
+def copy(src, dst):
+    """fio_copy of src into dst (device tensors of equal byte size) on the current stream."""
+    torch = _torch()
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb or not (src.is_cuda and dst.is_cuda):
+        raise ValueError("copy needs two device tensors of the same byte size")
+    stream = torch.cuda.current_stream(src.device).cuda_stream
+    _check(load_library().fio_copy(c_void_p(src.data_ptr()), c_void_p(dst.data_ptr()), nb, c_void_p(stream)))
+    return dst
 
 
 def autotune(N, phase, tol, params=(), B=1, precision="f32", max_tried=32):

@@ -1,0 +1,109 @@
+"""HBM traffic of the apply kernels from hardware byte counters.
+
+rocprofv3 --pmc writes one CSV row per (dispatch, counter).  FETCH_SIZE and
+WRITE_SIZE read the bytes the L2 fetched from and wrote to memory; their unit
+and coverage are calibrated here against the plain copy kernel k_copy16 of a
+known size that runs in the same process: factor = bytes it moved / counter
+reading.  A traffic record stores the digest of the kernel sources it was
+measured on, so a changed kernel invalidates it.
+
+    python -m paper_math_0610051_amd.pmc FETCH.csv WRITE.csv --copy-bytes B \
+        --kernel k_interp --out record.json [--meta key=value ...]
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+KERNEL_SOURCES = ("apply.hip", "apply.hpp", "common.hpp", "fft.hpp", "plan.hpp")
+
+
+def source_digest() -> str:
+    """sha256 over the sources that define the apply kernels."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def read_counter(path, counter):
+    """{kernel short name: [value per dispatch in dispatch order]} for one counter."""
+    rows = {}
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"]
+            short = name.split("(")[0].split("<")[0].split("::")[-1].replace("void ", "").strip()
+            rows.setdefault(short, []).append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+    return {k: [v for _, v in sorted(vs)] for k, vs in rows.items()}
+
+
+def traffic_record(fetch_csv, write_csv, copy_bytes, kernel, meta=None):
+    fetch = read_counter(fetch_csv, "FETCH_SIZE")
+    write = read_counter(write_csv, "WRITE_SIZE")
+    for tab, cname in ((fetch, "FETCH_SIZE"), (write, "WRITE_SIZE")):
+        if "k_copy16" not in tab or kernel not in tab:
+            raise SystemExit("%s: no k_copy16 or %s dispatches" % (cname, kernel))
+    f_copy = sum(fetch["k_copy16"]) / len(fetch["k_copy16"])
+    w_copy = sum(write["k_copy16"]) / len(write["k_copy16"])
+    f_scale, w_scale = copy_bytes / f_copy, copy_bytes / w_copy
+    fk = sum(fetch[kernel]) / len(fetch[kernel])
+    wk = sum(write[kernel]) / len(write[kernel])
+    rec = dict(kernel=kernel, source_digest=source_digest(), copy_bytes=copy_bytes,
+               fetch_counter_per_copy=f_copy, write_counter_per_copy=w_copy,
+               fetch_scale=f_scale, write_scale=w_scale,
+               dispatches=[len(fetch[kernel]), len(write[kernel])],
+               fetch_bytes=fk * f_scale, write_bytes=wk * w_scale,
+               traffic_bytes=fk * f_scale + wk * w_scale,
+               others={k: dict(fetch_bytes=sum(v) / len(v) * f_scale,
+                               write_bytes=(sum(write[k]) / len(write[k]) * w_scale) if k in write else None)
+                       for k, v in fetch.items() if k not in (kernel, "k_copy16")})
+    rec.update(meta or {})
+    return rec
+
+
+def load_traffic(path, kernel, **expect):
+    """Traffic bytes per launch from a stored record, or None if absent or stale."""
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel") != kernel or rec.get("source_digest") != source_digest():
+        return None
+    for k, v in expect.items():
+        if rec.get(k) != v:
+            return None
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("fetch_csv")
+    ap.add_argument("write_csv")
+    ap.add_argument("--copy-bytes", type=float, required=True)
+    ap.add_argument("--kernel", default="k_interp")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--meta", nargs="*", default=[])
+    a = ap.parse_args()
+    meta = {}
+    for kv in a.meta:
+        k, v = kv.split("=", 1)
+        try:
+            v = json.loads(v)
+        except ValueError:
+            pass
+        meta[k] = v
+    rec = traffic_record(a.fetch_csv, a.write_csv, a.copy_bytes, a.kernel, meta)
+    with open(a.out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -116,6 +116,10 @@ def test_null_handles(lib):
     assert lib.fio_destroy(None) == fio.FIO_OK
     assert lib.fio_plan_info(None, None) == fio.FIO_EINVAL
     assert lib.fio_apply_multi(0, None, None, None, None, None) == fio.FIO_EINVAL
+    # the copy helper rejects null, misaligned and ragged requests before any launch
+    assert lib.fio_copy(None, None, 16, None) == fio.FIO_EINVAL
+    assert lib.fio_copy(ctypes.c_void_p(4096), ctypes.c_void_p(8192), 17, None) == fio.FIO_EINVAL
+    assert lib.fio_copy(ctypes.c_void_p(4104), ctypes.c_void_p(8192), 32, None) == fio.FIO_EINVAL
 
 
 def test_python_binding_raises_without_device_tensor():
