@@ -15,7 +15,7 @@
  * evaluate each term with a type-2 NUFFT at the warped points
  * grad_xi Phi(x, xi_hat_ell) of a sheared, centred box, and combine with the
  * spatial factors gamma^x_{ell t}(x) (eq. (dfioalgo)).  The factors come from
- * the randomized separation of Section 3.3, built by fio_plan.
+ * the randomized separation of Section 3.2, built by fio_plan.
  *
  * Conventions shared by every entry point:
  *   - Arrays are plain device pointers (HIP device memory on the device that
@@ -128,7 +128,7 @@ typedef struct {
 
 void fio_default_options(fio_options *opt);
 
-/* Build a plan (Section 3.3 preprocessing: partition, shears, NUFFT set-up,
+/* Build a plan (Section 3.2 preprocessing: partition, shears, NUFFT set-up,
  * randomized separation with adaptive r, factor storage).  tol is the target
  * relative l2 error of the apply.  On success *out owns device memory. */
 fio_status fio_plan(int N, const fio_phase *phase, const fio_amplitude *amp, double tol, fio_plan_t *out);
@@ -230,7 +230,7 @@ fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp,
  * of wedge ell at phase scale s (the family's p0).  Weights are FP32 masters
  * fed to the BF16 matrix cores with FP32 accumulation; training and inference
  * run on the device that is current at creation.  Its targets are the
- * factors of the randomized separation (Section 3.3) with one column sample
+ * factors of the randomized separation (Section 3.2) with one column sample
  * per wedge shared by all training scales: alpha*_s(x) = A_s(x, C) V / s1,
  * V the leading 16 eigenvectors of the Gram matrix of A_s(:, C) summed over
  * the scales.  A plan built with opt.learned = this network (factor_mode

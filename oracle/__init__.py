@@ -12,7 +12,7 @@ Contents:
     OpenMP over output points (the definition oracle, the judge);
   * reference.py -- NumPy FP64: phase families, the dense operator matrix
     for tiny N, the wedge partition of Section 1.3, the residual phase,
-    the randomized separation of Section 3.3, a step-by-step model of the
+    the randomized separation of Section 3.2, a step-by-step model of the
     evaluation of Section 3.4 that uses direct nonuniform sums instead of a
     NUFFT, and the error estimators of Section 4;
   * mlp.py -- FP64 NumPy model of the factor network (forward, backward,

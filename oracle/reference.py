@@ -248,7 +248,7 @@ def residual_matrix(N, kind, p, theta, xidx, k1, k2):
 
 
 # --------------------------------------------------------------------------
-# Randomized separation (Section 3.3)
+# Randomized separation (Section 3.2)
 # --------------------------------------------------------------------------
 def randomized_separation(N, kind, p, theta, k1, k2, eps, rng, r0=48, accept=1.0 / 3.0):
     """Low-rank A ~ U T of A = exp(2 pi i Phi_ell) on X x W_ell, by the paper's steps.

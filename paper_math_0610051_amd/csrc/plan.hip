@@ -4,7 +4,7 @@
 //      into angular wedges;
 //   2. per wedge, an integer shear M and translation xi_c giving a small centred
 //      box (Section 3.4), and an oversampled FFT grid for the type-2 NUFFT;
-//   3. per wedge, the randomized separation of exp(2 pi i Phi_ell) (Section 3.3):
+//   3. per wedge, the randomized separation of exp(2 pi i Phi_ell) (Section 3.2):
 //      r sampled columns, their FP64 Gram matrix reduced on the GPU, a host
 //      Jacobi eigen-decomposition (the SVD of A_[C] through its Gram matrix),
 //      rank q from the singular-value threshold, r sampled rows and the
@@ -486,7 +486,7 @@ static double separation_estimate(const fio_plan_s *P, const WedgeHost &W, const
     return std::sqrt(num / std::max(den, 1e-300));
 }
 
-// Randomized separation of one wedge (Section 3.3) with verification.
+// Randomized separation of one wedge (Section 3.2) with verification.
 fio_status separate_wedge(fio_plan_s *P, int l, const double2 *d_xcoef, DeviceScratch &scr) {
     WedgeHost &W = P->wedges[l];
     const int N = P->N;

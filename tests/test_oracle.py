@@ -98,7 +98,7 @@ def test_grid_shift_is_exact_roll(m1, m2):
 
 @pytest.mark.parametrize("kind,p", [(1, [0.05]), (1, [-0.11]), (0, [0.0123, -0.371])])
 def test_fourier_multiplier_closed_form(kind, p):
-    """x-independent h: u = IDFT(e^{2 pi i h(xi)} DFT f) at centred xi (Section 1.1)."""
+    """x-independent h: u = IDFT(e^{2 pi i h(xi)} DFT f) at centred xi (Section 1, eq. (wave_solution))."""
     N = 32
     f = _field(N, 7)
     u = od.direct(N, kind, p, fi.fhat_from_f(f), np.arange(N * N)).reshape(N, N)
@@ -233,7 +233,7 @@ def test_corona_partition_covers_and_sums():
     assert np.max(np.abs(parts - full)) < 1e-12
 
 
-# ---------------------------------------------------------------- separation (Section 3.3)
+# ---------------------------------------------------------------- separation (Section 3.2)
 def test_rank_one_for_x_independent_h():
     """Phi = x.xi + h(xi): the residual depends on xi only, so the separation is exact at rank 1."""
     N, L = 32, 8
