@@ -103,11 +103,13 @@ def tuned_plan(N, tol, B, fixed=None):
         best, tried = autotune(N, "c1c2", tol, params=(1.0,), B=B)
         log("autotune %.1f s (%d candidates): %s" % (time.perf_counter() - t0, len(tried), best))
     else:
-        L, sg, st, nt = fixed
-        best = dict(n_wedges=int(L), sigma=float(sg), sep_tol_frac=float(st), nufft_tol_frac=float(nt))
+        L, sg, st, nt = fixed[:4]
+        best = dict(n_wedges=int(L), sigma=float(sg), sep_tol_frac=float(st), nufft_tol_frac=float(nt),
+                    kernel_width=int(fixed[4]) if len(fixed) > 4 else 0)
     t0 = time.perf_counter()
     plan = Plan(N, "c1c2", tol, params=(1.0,), max_batch=B, n_wedges=best["n_wedges"], sigma=best["sigma"],
-                sep_tol_frac=best["sep_tol_frac"], nufft_tol_frac=best["nufft_tol_frac"])
+                sep_tol_frac=best["sep_tol_frac"], nufft_tol_frac=best["nufft_tol_frac"],
+                kernel_width=best.get("kernel_width", 0))
     return plan, time.perf_counter() - t0, best
 
 
@@ -346,7 +348,7 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the per-RHS loop comparison")
-    ap.add_argument("--plan-params", default="", help="L,sigma,sep_tol_frac,nufft_tol_frac instead of autotuning")
+    ap.add_argument("--plan-params", default="", help="L,sigma,sep_tol_frac,nufft_tol_frac[,kernel_width] instead of autotuning")
     ap.add_argument("--traffic-record", default=os.path.join(ROOT, "profiles", "k_interp_traffic_N1024_B8_c1c2.json"))
     ap.add_argument("--learned-steps", type=int, default=6000)
     ap.add_argument("--learned-samples", type=int, default=4096)

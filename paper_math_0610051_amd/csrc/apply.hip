@@ -12,6 +12,7 @@
 //
 // Stages 1 and 2 run LDS-resident Stockham transforms; stage 3 is atomic-free:
 // each thread owns one output point and loops over all wedges.
+#include <cfloat>
 #include <climits>
 #include <cstring>
 
@@ -173,6 +174,88 @@ __device__ inline int wave_max(int v) {
         v = max(v, __shfl_xor(v, o));
     return v;
 }
+__device__ inline double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Grid coordinate u = m (y - k) and the first cell floor(u - w/2) + 1 of the
+// stencil, without floating-point contraction, so that every thread and the
+// window bounds map equal inputs to equal results; the map is monotone in y.
+template <int W>
+__device__ inline int stencil_origin(double m, double y, double k, double &u) {
+#pragma clang fp contract(off)
+    u = m * (y - k);
+    return (int)floor(u - 0.5 * W) + 1;
+}
+
+// Row stride (16-byte units) of the staged window.  A ds_read_b128 serves one
+// 16-lane quarter of a wave per cycle from 64 four-byte banks, i.e. 16 unit
+// residues: two different cells whose unit addresses agree mod 16 cost an
+// extra cycle, while lanes reading the same cell share it.  All lanes of one
+// stencil read are the lanes' base cells (d1, d2) shifted by a common offset,
+// so the conflicts follow from the base cells alone.  Each candidate stride
+// F2 .. F2 + 7 is scored per quarter-wave by the number of distinct cells
+// minus the number of distinct residues, summed over the workgroup; the
+// lowest score wins, ties going to the smaller stride.  Quarter-waves whose
+// cells spread beyond 16 x 4 are not scored.  Contains one block barrier.
+__device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int lane, int wave,
+                                      unsigned long long *red2) {
+    int m1 = active ? d1 : INT_MAX, m2 = active ? d2 : INT_MAX;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+        m1 = min(m1, __shfl_xor(m1, o));
+        m2 = min(m2, __shfl_xor(m2, o));
+    }
+    const int e1 = active ? d1 - m1 : 0, e2 = active ? d2 - m2 : 0;
+    const bool fits = e1 < 16 && e2 < 4;
+    unsigned long long cell = (active && fits) ? 1ull << (e1 * 4 + e2) : 0ull;
+    int wide = fits ? 0 : 1;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+        cell |= __shfl_xor(cell, o);
+        wide |= __shfl_xor(wide, o);
+    }
+    const int ncell = __popcll(cell);
+    unsigned long long packed = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        unsigned key = active ? 1u << ((e1 * (F2 + k) + e2) & 15) : 0u;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1)
+            key |= __shfl_xor(key, o);
+        const int score = wide ? 0 : ncell - __popc(key);  // 0..15 per quarter-wave
+        packed |= (unsigned long long)score << (8 * k);
+    }
+    // 8-bit fields: at most 4 x 4 x 15 = 240 per candidate over the workgroup
+    packed += __shfl_xor(packed, 16);
+    packed += __shfl_xor(packed, 32);
+    if (lane == 0)
+        red2[wave] = packed;
+    __syncthreads();
+    unsigned long long tot = 0;
+#pragma unroll
+    for (int k = 0; k < kThreads / 64; ++k)
+        tot += red2[k];
+    int best = 0, bs = 1 << 30;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int sc = (int)((tot >> (8 * k)) & 0xFF);
+        if (sc < bs) {
+            bs = sc;
+            best = k;
+        }
+    }
+    return F2 + best;
+}
 
 template <typename T, int W>
 __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__restrict__ u, long long ustride, int B,
@@ -183,7 +266,8 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
     constexpr int kOff = kUnits / kThreads;          // staged units of one plane per thread
     extern __shared__ unsigned char smem_raw[];
     U *win = reinterpret_cast<U *>(smem_raw);
-    __shared__ int red[kThreads / 64][4];
+    __shared__ double red[kThreads / 64][4];
+    __shared__ unsigned long long red2[kThreads / 64];
     const int N = a.N;
     const int tiles2 = (N + kTileX - 1) / kTileX;
     const int T1 = (tile / tiles2) * kTileX, T2 = (tile % tiles2) * kTileX;
@@ -196,9 +280,7 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
     const bool active = n1 < N && n2 < N;
     const long long p = (long long)n1 * N + n2;
     const double x1 = (double)n1 / N, x2 = (double)n2 / N;
-    const double r1 = (double)T1 / N, r2 = (double)T2 / N;
     const XCoef c = phase_xcoef(a.phase, x1, x2);
-    const XCoef cr = phase_xcoef(a.phase, r1, r2);
     cplx<T> acc[kInterpBatch];
 #pragma unroll
     for (int b = 0; b < kInterpBatch; ++b)
@@ -208,34 +290,23 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         if (wd.q == 0)
             continue;
         const int m1 = wd.n1, m2 = wd.n2, q = wd.q, qu = q / CPU;
-        double g1, g2, h1, h2;
+        double g1, g2;
         phase_grad(a.phase, c, wd.e1, wd.e2, g1, g2);
-        phase_grad(a.phase, cr, wd.e1, wd.e2, h1, h2);
         const double y1 = x1 + g1, y2 = x2 + g2;
-        const double ry1 = r1 + h1, ry2 = r2 + h2;
         const double yp1 = wd.mt[0] * y1 + wd.mt[1] * y2;
         const double yp2 = wd.mt[2] * y1 + wd.mt[3] * y2;
-        const double k1 = floor(wd.mt[0] * ry1 + wd.mt[1] * ry2);
-        const double k2 = floor(wd.mt[2] * ry1 + wd.mt[3] * ry2);
         double psi = wd.cvec[0] * y1 + wd.cvec[1] * y2;
         psi -= rint(psi);
         T cs, sn;
         expi_t<T>(psi, cs, sn);
-        // grid coordinates unwrapped around the tile's corner point
-        const double u1 = m1 * (yp1 - k1), u2 = m2 * (yp2 - k2);
-        const int j1 = (int)floor(u1 - 0.5 * W) + 1;
-        const int j2 = (int)floor(u2 - 0.5 * W) + 1;
-        const T f1 = (T)(u1 - j1), f2 = (T)(u2 - j2);
-        T w1[W], w2[W];
-#pragma unroll
-        for (int i = 0; i < W; ++i) {
-            w1[i] = es_kernel<T>(f1 - T(i), a.two_over_w, a.beta);
-            w2[i] = es_kernel<T>(f2 - T(i), a.two_over_w, a.beta);
-        }
-        // window of the tile's stencils
+        // Extent of the tile's points in the (unreduced) sheared coordinates.
+        // The tile's grid coordinates are unwrapped around floor of the
+        // smallest coordinate, so the periodic wrap cannot split its window;
+        // the stencil origin is monotone in the coordinate, so the window
+        // bounds follow from the extreme points with the same arithmetic.
         {
-            const int mn1 = wave_min(active ? j1 : INT_MAX), mx1 = wave_max(active ? j1 : INT_MIN);
-            const int mn2 = wave_min(active ? j2 : INT_MAX), mx2 = wave_max(active ? j2 : INT_MIN);
+            const double mn1 = wave_min(active ? yp1 : DBL_MAX), mx1 = wave_max(active ? yp1 : -DBL_MAX);
+            const double mn2 = wave_min(active ? yp2 : DBL_MAX), mx2 = wave_max(active ? yp2 : -DBL_MAX);
             if (lane == 0) {
                 red[wave][0] = mn1;
                 red[wave][1] = mx1;
@@ -244,17 +315,29 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
             }
         }
         __syncthreads();
-        int J1 = red[0][0], X1 = red[0][1], J2 = red[0][2], X2 = red[0][3];
+        double lo1 = red[0][0], hi1 = red[0][1], lo2 = red[0][2], hi2 = red[0][3];
 #pragma unroll
         for (int k = 1; k < kThreads / 64; ++k) {
-            J1 = min(J1, red[k][0]);
-            X1 = max(X1, red[k][1]);
-            J2 = min(J2, red[k][2]);
-            X2 = max(X2, red[k][3]);
+            lo1 = fmin(lo1, red[k][0]);
+            hi1 = fmax(hi1, red[k][1]);
+            lo2 = fmin(lo2, red[k][2]);
+            hi2 = fmax(hi2, red[k][3]);
         }
-        __syncthreads();
+        const double k1 = floor(lo1), k2 = floor(lo2);
+        double u1, u2, ue;
+        const int j1 = stencil_origin<W>(m1, yp1, k1, u1), j2 = stencil_origin<W>(m2, yp2, k2, u2);
+        const int J1 = stencil_origin<W>(m1, lo1, k1, ue), X1 = stencil_origin<W>(m1, hi1, k1, ue);
+        const int J2 = stencil_origin<W>(m2, lo2, k2, ue), X2 = stencil_origin<W>(m2, hi2, k2, ue);
+        const T f1 = (T)(u1 - j1), f2 = (T)(u2 - j2);
+        T w1[W], w2[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            w1[i] = es_kernel<T>(f1 - T(i), a.two_over_w, a.beta);
+            w2[i] = es_kernel<T>(f2 - T(i), a.two_over_w, a.beta);
+        }
         const int F1 = X1 - J1 + W, F2 = X2 - J2 + W;
-        const int S2 = F2 | 1;                   // odd LDS row stride (units) spreads rows over the banks
+        // the barrier in pick_row_stride also separates these reads of red from the next wedge's writes
+        const int S2 = pick_row_stride(active, j1 - J1, j2 - J2, F2, lane, wave, red2);
         const int plane = F1 * S2;               // units of one rank-pair plane of the window
         const int ppr = kUnits / plane;          // planes staged per round
         const bool staged = ppr >= 1 && F1 <= m1 && F2 <= m2;
@@ -400,14 +483,20 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
     }
 }
 
+// FP32: at most 168 VGPRs, so that three workgroups share a SIMD (the
+// compiler otherwise hoists whole stencil planes into registers); FP64 keeps
+// the default budget, which it needs to avoid spills.
+template <typename T>
+constexpr int kInterpWavesPerEU = sizeof(T) == 4 ? 3 : 1;
+
 template <typename T, int W>
-__global__ __launch_bounds__(kThreads) void k_interp(PlanArgs<T> a, cplx<T> *__restrict__ u, long long ustride,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T>))) void k_interp(PlanArgs<T> a, cplx<T> *__restrict__ u, long long ustride,
                                                      int B, int bofs, int l0, int l1) {
     interp_body<T, W>(a, u, ustride, B, bofs, l0, l1, blockIdx.x);
 }
 
 template <typename T, int W>
-__global__ __launch_bounds__(kThreads) void k_interp_multi(const InstArgs<T> *__restrict__ inst,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T>))) void k_interp_multi(const InstArgs<T> *__restrict__ inst,
                                                            const MultiTile *__restrict__ tiles) {
     const MultiTile m = tiles[blockIdx.x];
     const InstArgs<T> &I = inst[m.inst];

@@ -235,7 +235,12 @@ fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp,
     if (cache_lookup(cache, key, best))
         return FIO_OK;
     const int L0 = o.n_wedges > 0 ? o.n_wedges : 8 * (int)std::ceil(std::sqrt((double)N) / 8.0);
-    const int Ls[] = {std::max(8, L0 - 8), L0, L0 + 8, L0 + 16};
+    // fewer wedges rarely pay at large N, where ranks grow fastest with the angular width
+    std::vector<int> Ls;
+    if (N <= 256)
+        Ls.push_back(std::max(8, L0 - 8));
+    for (int L : {L0, L0 + 8, L0 + 16})
+        Ls.push_back(L);
     const double splits[][2] = {{0.25, 0.1}, {0.4, 0.15}};
     const double sigmas[] = {2.0, 2.5};
     const size_t es = o.precision == FIO_F64 ? 16 : 8;
@@ -257,15 +262,31 @@ fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp,
     bool have = false;
     int count = 0;
     fio_status result = FIO_OK;
+    // kernel widths: the one the NUFFT tolerance asks for, and the next
+    // compiled width below it (the width formula is a bound; the probe decides)
+    auto widths = [&](double eps, double sg) {
+        int w = 0;
+        double beta = 0;
+        es_parameters(eps, sg, 0, w, beta);
+        std::vector<int> ws{w};
+        int lower = 0;
+        for (int v : kInterpWidths)
+            if (v < w)
+                lower = v;
+        if (lower >= 4)
+            ws.push_back(lower);
+        return ws;
+    };
     for (double sg : sigmas)
         for (const auto &sp : splits)
+            for (int kw : widths(tol * sp[1], sg))
             for (int L : Ls) {
                 fio_options c = o;
                 c.n_wedges = L;
                 c.sigma = sg;
                 c.sep_tol_frac = sp[0];
                 c.nufft_tol_frac = sp[1];
-                c.kernel_width = 0;
+                c.kernel_width = kw;
                 c.max_batch = std::max(c.max_batch, B);
                 fio_plan_t P = nullptr;
                 fio_status st = fio_plan_ex(N, phase, amp, tol, &c, &P);
