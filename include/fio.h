@@ -52,8 +52,8 @@ typedef enum {
     FIO_EINVAL = -1,    /* bad argument: odd or too small N, null pointer, tol outside (0,1), ... */
     FIO_ENOMEM = -2,    /* device or host allocation failed */
     FIO_EDEVICE = -3,   /* a HIP call failed (message has the HIP error string) */
-    FIO_EACCURACY = -4, /* a forced factor mode could not meet the tolerance */
-    FIO_ENOTSUP = -5    /* valid but unsupported request (e.g. amplitude kind, FP32 below its floor) */
+    FIO_EACCURACY = -4, /* the separation (exact or forced learned) could not meet the tolerance */
+    FIO_ENOTSUP = -5    /* valid but unsupported request (e.g. amplitude kind, tol below 5e-7) */
 } fio_status;
 
 /* Phase families Phi(x, xi) = x.xi + h(x, xi), h homogeneous of degree 1 in xi.
@@ -130,7 +130,11 @@ void fio_default_options(fio_options *opt);
 
 /* Build a plan (Section 3.2 preprocessing: partition, shears, NUFFT set-up,
  * randomized separation with adaptive r, factor storage).  tol is the target
- * relative l2 error of the apply.  On success *out owns device memory. */
+ * relative l2 error of the apply, at least 5e-7 in either precision (the
+ * separation reads singular values off the FP64 Gram matrix of the sampled
+ * columns), else FIO_ENOTSUP.  FIO_EACCURACY if a wedge's separation error
+ * estimate stays above tol after the verification retries.  On success *out
+ * owns device memory. */
 fio_status fio_plan(int N, const fio_phase *phase, const fio_amplitude *amp, double tol, fio_plan_t *out);
 fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, double tol,
                        const fio_options *opt /* nullable */, fio_plan_t *out);

@@ -129,8 +129,11 @@ fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, 
         return (set_error("option out of range"), FIO_EINVAL);
     if (!(o.sep_tol_frac > 0 && o.sep_tol_frac <= 1) || !(o.nufft_tol_frac > 0 && o.nufft_tol_frac <= 1))
         return (set_error("tolerance fractions must lie in (0, 1]"), FIO_EINVAL);
-    if (o.precision == FIO_F32 && tol < 5e-7)
-        return (set_error("tol below the FP32 floor (5e-7); use FIO_F64"), FIO_ENOTSUP);
+    // the separation reads singular values off the eigenvalues of the FP64
+    // Gram matrix of the sampled columns, which resolves them down to about
+    // 1e-7 of the largest (its threshold is tol * sep_tol_frac)
+    if (tol < 5e-7)
+        return (set_error("tol below the floor (5e-7) of the Gram-matrix separation"), FIO_ENOTSUP);
     if (o.factor_mode == FIO_FACTORS_LEARNED && !o.learned)
         return (set_error("FIO_FACTORS_LEARNED needs a trained network"), FIO_EINVAL);
     fio_plan_s *P = new (std::nothrow) fio_plan_s();

@@ -21,9 +21,11 @@
 namespace fio {
 
 // ---------------------------------------------------------------------------
-// Stage 1: window x factor -> box row, FFT along axis 2 (length n2, the short
-// side of the box).  One workgroup per (wedge, box row, rank chunk); loops
-// over the batch; in-place LDS transform.
+// Stage 1: window x factor -> box rows, FFT along axis 2 (length n2, the short
+// side of the box).  One workgroup per (wedge, nr adjacent box rows, rank
+// chunk); loops over the batch; in-place LDS transform of nr * tn sequences.
+// H is stored column-major in cells, [j2][k1][rank], so the nr rows of one
+// column j2 leave as one contiguous run.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it, const cplx<T> *__restrict__ fhat,
@@ -32,57 +34,65 @@ __device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
     const WedgeDev &W = a.wedges[it.l];
-    const int n = W.n2, nb = it.tn, q = W.q, B2 = W.B2, lo2 = W.lo2;
+    const int n = W.n2, nr = it.nr, tn = it.tn, nbt = nr * tn, q = W.q, B1 = W.B1, B2 = W.B2, lo2 = W.lo2;
     const int tid = threadIdx.x, nt = blockDim.x;
     const FftPlan *pl = a.fftplans + W.fft2;
-    const cplx<T> *tw = a.tw + W.tw2;
+    cplx<T> *twl = buf + n * nbt;  // the n twiddles follow the transform buffer
+    for (int i = tid; i < n; i += nt)
+        twl[i] = a.tw[W.tw2 + i];
+    const FastDiv ftn((unsigned)tn), fb2((unsigned)B2), fnbt((unsigned)nbt);
     const int *map = a.map + W.map_off + (long long)it.k1 * B2;
     const int *omega = a.omega + W.mem_off;
     const cplx<T> *gxi = a.gxi + W.gxi_off + it.t0;
     for (int b = 0; b < B; ++b) {
-        for (int i = tid; i < n * nb; i += nt)
+        for (int i = tid; i < n * nbt; i += nt)
             buf[i] = cmake<T>(0, 0);
         __syncthreads();
         const cplx<T> *f = fhat + b * fstride;
-        for (int i = tid; i < B2 * nb; i += nt) {
-            const int k2 = i / nb, t = i - k2 * nb;
-            const int m = map[k2];
+        // (row r, box column k2, rank t), rank fastest
+        for (int i = tid; i < nr * B2 * tn; i += nt) {
+            const int rk = ftn.div(i), t = i - rk * tn;
+            const int r = fb2.div(rk), k2 = rk - r * B2;
+            const int m = map[r * B2 + k2];
             if (m >= 0) {
                 int j2 = lo2 + k2;
                 if (j2 < 0)
                     j2 += n;
-                buf[j2 * nb + t] = cmul(f[omega[m]], gxi[(long long)m * q + t]);
+                buf[j2 * nbt + r * tn + t] = cmul(f[omega[m]], gxi[(long long)m * q + t]);
             }
         }
         __syncthreads();
-        fft_inplace<T, E>(buf, pl, n, nb, tw, tid, nt);
-        cplx<T> *H = a.H + b * a.H_stride + W.H_off + (long long)it.k1 * n * q + it.t0;
-        for (int i = tid; i < n * nb; i += nt) {
-            const int j2 = i / nb, t = i - j2 * nb;
-            H[(long long)j2 * q + t] = buf[i];
+        fft_inplace<T, E>(buf, pl, n, nbt, fnbt, twl, tid, nt);
+        // buf[j2 * nbt + r * tn + t] -> H[(j2 * B1 + k1 + r) * q + t0 + t]
+        cplx<T> *H = a.H + b * a.H_stride + W.H_off + (long long)it.k1 * q + it.t0;
+        for (int i = tid; i < n * nbt; i += nt) {
+            const int j2 = fnbt.div(i), c = i - j2 * nbt, r = ftn.div(c), t = c - r * tn;
+            H[((long long)j2 * B1 + r) * q + t] = buf[i];
         }
         __syncthreads();
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_rows(PlanArgs<T> a, const RowItem *__restrict__ items,
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kFftWavesPerEU))) void k_rows(PlanArgs<T> a, const RowItem *__restrict__ items,
                                                       const cplx<T> *__restrict__ fhat, long long fstride, int B) {
     rows_body<T>(a, items[blockIdx.x], fhat, fstride, B);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_rows_multi(const InstArgs<T> *__restrict__ inst,
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kFftWavesPerEU))) void k_rows_multi(const InstArgs<T> *__restrict__ inst,
                                                             const MultiRowItem *__restrict__ items) {
     const MultiRowItem m = items[blockIdx.x];
     const InstArgs<T> &I = inst[m.inst];
-    rows_body<T>(I.a, RowItem{m.l, m.k1, m.t0, m.tn}, I.fhat, (long long)I.a.N * I.a.N, I.B);
+    rows_body<T>(I.a, RowItem{m.l, m.k1, m.nr, m.t0, m.tn, 0}, I.fhat, (long long)I.a.N * I.a.N, I.B);
 }
 
 // ---------------------------------------------------------------------------
-// Stage 2: FFT along axis 1 (length n1, the long side) of nb adjacent
-// transforms tau = j2 * q + t; rows outside the box are the implicit zero
-// padding.  In-place LDS transform.
+// Stage 2: FFT along axis 1 (length n1, the long side) of nb transforms
+// tau = j2 * q + t, tau0 <= tau < tau0 + nb; rows outside the box are the
+// implicit zero padding.  Items hold whole cell columns (nb a multiple of q,
+// tau0 aligned) or a rank range of one column.  With H [j2][k1][rank] and
+// G [j2][j1][rank] a whole-column item reads and writes contiguous runs.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it, int b) {
@@ -90,38 +100,64 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
     const WedgeDev &W = a.wedges[it.l];
-    const int n = W.n1, nb = it.nb, B1 = W.B1, lo1 = W.lo1;
-    const long long rs = (long long)W.n2 * W.q;  // row stride of H and G
+    const int n = W.n1, nb = it.nb, B1 = W.B1, lo1 = W.lo1, q = W.q;
     const int tid = threadIdx.x, nt = blockDim.x;
     const FftPlan *pl = a.fftplans + W.fft1;
-    const cplx<T> *tw = a.tw + W.tw1;
+    cplx<T> *twl = buf + n * nb;  // the n twiddles follow the transform buffer
+    for (int i = tid; i < n; i += nt)
+        twl[i] = a.tw[W.tw1 + i];
     for (int i = tid; i < n * nb; i += nt)
         buf[i] = cmake<T>(0, 0);
+    const FastDiv fnb((unsigned)nb), fq((unsigned)q), fb1((unsigned)B1), fn((unsigned)n);
     __syncthreads();
-    const cplx<T> *H = a.H + b * a.H_stride + W.H_off + it.tau0;
-    for (int i = tid; i < B1 * nb; i += nt) {
-        const int k1 = i / nb, c = i - k1 * nb;
-        int j1 = lo1 + k1;
-        if (j1 < 0)
-            j1 += n;
-        buf[j1 * nb + c] = H[k1 * rs + c];
+    const cplx<T> *H = a.H + b * a.H_stride + W.H_off;
+    cplx<T> *G = a.G + b * a.G_stride + W.G_off;
+    const bool whole = nb >= q;  // whole columns: tau0 = j2_0 * q, nb = ncol * q
+    const int j20 = it.tau0 / q, t0 = it.tau0 - j20 * q;
+    if (whole) {
+        // flat i = (col * B1 + k1) * q + t over the columns' contiguous runs
+        const cplx<T> *src = H + (long long)it.tau0 * B1;
+        for (int i = tid; i < B1 * nb; i += nt) {
+            const int kq = fq.div(i), t = i - kq * q;  // kq = col * B1 + k1
+            const int col = fb1.div(kq), k1 = kq - col * B1;
+            int j1 = lo1 + k1;
+            if (j1 < 0)
+                j1 += n;
+            buf[j1 * nb + col * q + t] = src[i];
+        }
+    } else {
+        for (int i = tid; i < B1 * nb; i += nt) {
+            const int k1 = fnb.div(i), c = i - k1 * nb;
+            int j1 = lo1 + k1;
+            if (j1 < 0)
+                j1 += n;
+            buf[j1 * nb + c] = H[((long long)j20 * B1 + k1) * q + t0 + c];
+        }
     }
     __syncthreads();
-    fft_inplace<T, E>(buf, pl, n, nb, tw, tid, nt);
-    cplx<T> *G = a.G + b * a.G_stride + W.G_off + it.tau0;
-    for (int i = tid; i < n * nb; i += nt) {
-        const int j1 = i / nb, c = i - j1 * nb;
-        G[j1 * rs + c] = buf[i];
+    fft_inplace<T, E>(buf, pl, n, nb, fnb, twl, tid, nt);
+    if (whole) {
+        cplx<T> *dstp = G + (long long)it.tau0 * n;
+        for (int i = tid; i < n * nb; i += nt) {
+            const int jq = fq.div(i), t = i - jq * q;  // jq = col * n + j1
+            const int col = fn.div(jq), j1 = jq - col * n;
+            dstp[i] = buf[j1 * nb + col * q + t];
+        }
+    } else {
+        for (int i = tid; i < n * nb; i += nt) {
+            const int j1 = fnb.div(i), c = i - j1 * nb;
+            G[((long long)j20 * n + j1) * q + t0 + c] = buf[i];
+        }
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_cols(PlanArgs<T> a, const ColItem *__restrict__ items) {
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kFftWavesPerEU))) void k_cols(PlanArgs<T> a, const ColItem *__restrict__ items) {
     cols_body<T>(a, items[blockIdx.x], blockIdx.y);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_cols_multi(const InstArgs<T> *__restrict__ inst,
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kFftWavesPerEU))) void k_cols_multi(const InstArgs<T> *__restrict__ inst,
                                                             const MultiColItem *__restrict__ items) {
     const MultiColItem m = items[blockIdx.x];
     cols_body<T>(inst[m.inst].a, ColItem{m.l, m.tau0, m.nb, 0}, m.b);
@@ -345,7 +381,8 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         const cplx<T> mod = cmake(cs, sn);
         const cplx<T> *G0 = a.G + (long long)bofs * a.G_stride + wd.G_off;
         if (staged) {
-            // source offsets (complex, rank 0) and window positions of this thread's cells
+            // source offsets (complex, rank 0) and window positions of this
+            // thread's cells, in column-major cell order (G is [j2][j1][rank])
             int off[kOff], dst[kOff];
             int c0 = J2 % m2;
             if (c0 < 0)
@@ -356,14 +393,14 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                 off[k] = -1;
                 dst[k] = 0;
                 if (e < F1 * F2) {
-                    const int rr = e / F2, cc = e - rr * F2;
+                    const int cc = e / F1, rr = e - cc * F1;
                     int gr = (J1 + rr) % m1;
                     if (gr < 0)
                         gr += m1;
                     int gc = c0 + cc;
                     if (gc >= m2)
                         gc -= m2;
-                    off[k] = (gr * m2 + gc) * q;
+                    off[k] = (gc * m1 + gr) * q;
                     dst[k] = rr * S2 + cc;
                 }
             }
@@ -449,14 +486,14 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                         int r1 = g1i + i1;
                         if (r1 >= m1)
                             r1 -= m1;
-                        const cplx<T> *row = G + (long long)r1 * m2 * q + t;
+                        const cplx<T> *row = G + (long long)r1 * q + t;
                         cplx<T> rs = cmake<T>(0, 0);
 #pragma unroll
                         for (int i2 = 0; i2 < W; ++i2) {
                             int r2 = g2i + i2;
                             if (r2 >= m2)
                                 r2 -= m2;
-                            const cplx<T> g = row[(long long)r2 * q];
+                            const cplx<T> g = row[(long long)r2 * m1 * q];
                             rs.re += w2[i2] * g.re;
                             rs.im += w2[i2] * g.im;
                         }

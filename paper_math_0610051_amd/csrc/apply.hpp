@@ -12,8 +12,9 @@ constexpr int kInterpBatch = 8;     // right-hand sides per interpolation launch
 constexpr int kTileX = 16;          // interpolation tile: kTileX x kTileX output points per workgroup
 constexpr int kInterpLdsBytes = 32768;  // LDS window of one wedge's grid per interpolation workgroup
 constexpr int kMaxLdsBytes = 131072;  // largest dynamic LDS request of any apply kernel
-constexpr int kFftThreads = 1024;     // workgroup size of the two FFT stages
-constexpr int kFftLdsBytes = 65536;   // in-place FFT buffer of one workgroup
+constexpr int kFftThreads = 512;     // workgroup size of the two FFT stages
+constexpr int kFftWavesPerEU = 4;    // register budget: two FFT workgroups per CU overlap load, transform and store
+constexpr int kFftLdsBytes = 32768;   // in-place FFT buffer of one workgroup (two workgroups per CU)
 constexpr int kInterpWidths[] = {4, 5, 6, 7, 8, 10, 12, 14, 16};
 
 // Per-instance arguments of the multi-instance kernels.
@@ -25,7 +26,7 @@ struct InstArgs {
     int B;
 };
 struct MultiRowItem {
-    int inst, l, k1, t0, tn, pad;
+    int inst, l, k1, nr, t0, tn;
 };
 struct MultiColItem {
     int inst, l, tau0, nb, b, pad;

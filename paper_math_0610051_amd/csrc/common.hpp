@@ -77,6 +77,28 @@ struct Phase {
     double p[8];
 };
 
+// Division of integers 0 <= x < 2^31 by an invariant divisor d >= 1 with a
+// multiply-high and a shift (Granlund and Montgomery, "Division by invariant
+// integers using multiplication", 1994): with l = ceil(log2 d) and
+// m = ceil(2^(31 + l) / d), x / d = mulhi(x, m) >> (l - 1); d = 1 passes x.
+// Used wherever a kernel splits flat indices by run-time extents.
+struct FastDiv {
+    unsigned d = 1, m = 0, s = 0;
+    FastDiv() = default;
+    __host__ __device__ explicit FastDiv(unsigned dd) : d(dd) {
+        unsigned l = 0;
+        while (l < 31 && (1u << l) < dd)
+            ++l;
+        if (l > 0) {
+            m = (unsigned)((((unsigned long long)1 << (31 + l)) + dd - 1) / dd);
+            s = l - 1;
+        }
+    }
+    __device__ __forceinline__ int div(int x) const {
+        return d == 1 ? x : (int)(__umulhi((unsigned)x, m) >> s);
+    }
+};
+
 struct XCoef {
     double a, b;
 };

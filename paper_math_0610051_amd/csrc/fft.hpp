@@ -1,7 +1,5 @@
 // Mixed-radix Stockham FFT passes (radices 2, 3, 4, 5, 8) used by the
-// oversampled-grid transforms of the type-2 NUFFT.  The same pass code runs
-// in LDS inside the kernels and on the host (for the library's self-check
-// entry point), so it is written against plain pointers.
+// oversampled-grid transforms of the type-2 NUFFT, run in place in LDS.
 //
 // Layout: nb transforms of length n are interleaved, element j of transform
 // b at index j*nb + b, so that consecutive lanes touch consecutive words.
@@ -16,10 +14,12 @@ namespace fio {
 constexpr int kMaxPasses = 24;
 
 // Radix plan of a length n = 2^a 3^b 5^c: radix 8 first, then 4/2, 3, 5.
+// ns[p] divides flat butterfly indices by Ns = radix[0] * ... * radix[p-1].
 struct FftPlan {
     int n;
     int npass;
     int radix[kMaxPasses];
+    FastDiv ns[kMaxPasses];
 };
 
 inline bool fft_make_plan(int n, FftPlan &pl) {
@@ -47,6 +47,11 @@ inline bool fft_make_plan(int n, FftPlan &pl) {
     while (m % 5 == 0 && pl.npass < kMaxPasses) {
         pl.radix[pl.npass++] = 5;
         m /= 5;
+    }
+    int Ns = 1;
+    for (int p = 0; p < pl.npass; ++p) {
+        pl.ns[p] = FastDiv((unsigned)Ns);
+        Ns *= pl.radix[p];
     }
     return m == 1;
 }
@@ -168,74 +173,21 @@ __host__ __device__ inline void dft_small<float, 5>(cplx<float> *v) { dft5(v); }
 template <>
 __host__ __device__ inline void dft_small<double, 5>(cplx<double> *v) { dft5(v); }
 
-// One butterfly of a Stockham pass of radix R (decimation in time):
-// inputs in[(j + r m) nb + b], twiddled by W_n^{r k n/(Ns R)} with k = j mod Ns,
-// outputs to out[((j / Ns) Ns R + k + s Ns) nb + b].  tw[i] = exp(+2 pi i i / n).
-template <typename T, int R>
-__host__ __device__ inline void stockham_butterfly(const cplx<T> *in, cplx<T> *out, int n, int nb, int Ns,
-                                                   const cplx<T> *tw, int work) {
-    const int m = n / R;
-    const int b = work % nb;
-    const int j = work / nb;
-    const int k = j % Ns;
-    const int tstep = (n / (Ns * R)) * k;
-    cplx<T> v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        cplx<T> x = in[(j + r * m) * nb + b];
-        v[r] = (r == 0 || k == 0) ? x : cmul(x, tw[r * tstep]);
-    }
-    dft_small<T, R>(v);
-    const int base = (j / Ns) * Ns * R + k;
-#pragma unroll
-    for (int s = 0; s < R; ++s)
-        out[(base + s * Ns) * nb + b] = v[s];
-}
-
-// One full pass executed by `nthreads` cooperating workers (tid in [0, nthreads)).
-template <typename T>
-__host__ __device__ inline void stockham_pass(int R, const cplx<T> *in, cplx<T> *out, int n, int nb, int Ns,
-                                              const cplx<T> *tw, int tid, int nthreads) {
-    const int total = (n / R) * nb;
-    switch (R) {
-    case 8:
-        for (int w = tid; w < total; w += nthreads)
-            stockham_butterfly<T, 8>(in, out, n, nb, Ns, tw, w);
-        break;
-    case 4:
-        for (int w = tid; w < total; w += nthreads)
-            stockham_butterfly<T, 4>(in, out, n, nb, Ns, tw, w);
-        break;
-    case 2:
-        for (int w = tid; w < total; w += nthreads)
-            stockham_butterfly<T, 2>(in, out, n, nb, Ns, tw, w);
-        break;
-    case 3:
-        for (int w = tid; w < total; w += nthreads)
-            stockham_butterfly<T, 3>(in, out, n, nb, Ns, tw, w);
-        break;
-    default:
-        for (int w = tid; w < total; w += nthreads)
-            stockham_butterfly<T, 5>(in, out, n, nb, Ns, tw, w);
-        break;
-    }
-}
-
-#ifdef __HIP_DEVICE_COMPILE__
-#define FIO_BARRIER() __syncthreads()
-#else
-#define FIO_BARRIER() ((void)0)
-#endif
-
-// In-place Stockham pass on a single LDS buffer: every worker reads and
-// transforms its butterflies into registers, the workgroup synchronises, and
-// the results are written back (then synchronises again).  KB bounds the
-// butterflies per worker: (n / R) * nb <= KB * nthreads must hold.
+// In-place Stockham pass of radix R (decimation in time) on one LDS buffer.
+// Butterfly w = j * nb + b reads buf[(j + r m) nb + b], r < R, m = n / R,
+// twiddles input r by W^(r k n / (Ns R)) with k = j mod Ns, W = exp(2 pi i / n),
+// and writes output s to buf[((j / Ns) Ns R + k + s Ns) nb + b].  Every worker
+// first transforms its butterflies into registers, the workgroup
+// synchronises, the results are written back, and it synchronises again.
+// KB bounds the butterflies per worker: (n / R) * nb <= KB * nthreads.
+// twl: the n twiddles W^i, i < n, in LDS.
 template <typename T, int R, int KB>
-__device__ __forceinline__ void stockham_pass_inplace(cplx<T> *buf, int n, int nb, int Ns, const cplx<T> *tw, int tid,
-                                             int nthreads) {
+__device__ __forceinline__ void stockham_pass_inplace(cplx<T> *buf, int n, int nb, const FastDiv &fnb, int Ns,
+                                                      const FastDiv &fns, const cplx<T> *twl, int tid,
+                                                      int nthreads) {
     const int m = n / R;
     const int total = m * nb;
+    const int tfac = m / Ns;  // n / (Ns R)
     cplx<T> v[KB][R];
     int dst[KB];
 #pragma unroll
@@ -243,20 +195,19 @@ __device__ __forceinline__ void stockham_pass_inplace(cplx<T> *buf, int n, int n
         const int w = tid + k * nthreads;
         dst[k] = -1;
         if (w < total) {
-            const int b = w % nb;
-            const int j = w / nb;
-            const int kk = j % Ns;
-            const int tstep = (n / (Ns * R)) * kk;
+            const int j = fnb.div(w), b = w - j * nb;
+            const int jq = fns.div(j), kk = j - jq * Ns;
+            const int tstep = tfac * kk;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const cplx<T> x = buf[(j + r * m) * nb + b];
-                v[k][r] = (r == 0 || kk == 0) ? x : cmul(x, tw[r * tstep]);
+                v[k][r] = (r == 0 || kk == 0) ? x : cmul(x, twl[r * tstep]);
             }
             dft_small<T, R>(v[k]);
-            dst[k] = ((j / Ns) * Ns * R + kk) * nb + b;
+            dst[k] = (jq * Ns * R + kk) * nb + b;
         }
     }
-    FIO_BARRIER();
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < KB; ++k)
         if (dst[k] >= 0) {
@@ -264,33 +215,34 @@ __device__ __forceinline__ void stockham_pass_inplace(cplx<T> *buf, int n, int n
             for (int s = 0; s < R; ++s)
                 buf[dst[k] + s * Ns * nb] = v[k][s];
         }
-    FIO_BARRIER();
+    __syncthreads();
 }
 
 // All passes of a length-n transform of nb interleaved sequences in place;
 // E = elements per worker the buffer holds at most (n * nb <= E * nthreads).
 template <typename T, int E>
-__device__ __forceinline__ void fft_inplace(cplx<T> *buf, const FftPlan *pl, int n, int nb, const cplx<T> *tw, int tid,
-                                   int nthreads) {
+__device__ __forceinline__ void fft_inplace(cplx<T> *buf, const FftPlan *pl, int n, int nb, const FastDiv &fnb,
+                                            const cplx<T> *twl, int tid, int nthreads) {
     int Ns = 1;
     const int npass = pl->npass;
     for (int p = 0; p < npass; ++p) {
         const int R = pl->radix[p];
+        const FastDiv fns = pl->ns[p];
         switch (R) {
         case 8:
-            stockham_pass_inplace<T, 8, (E + 7) / 8>(buf, n, nb, Ns, tw, tid, nthreads);
+            stockham_pass_inplace<T, 8, (E + 7) / 8>(buf, n, nb, fnb, Ns, fns, twl, tid, nthreads);
             break;
         case 4:
-            stockham_pass_inplace<T, 4, (E + 3) / 4>(buf, n, nb, Ns, tw, tid, nthreads);
+            stockham_pass_inplace<T, 4, (E + 3) / 4>(buf, n, nb, fnb, Ns, fns, twl, tid, nthreads);
             break;
         case 2:
-            stockham_pass_inplace<T, 2, (E + 1) / 2>(buf, n, nb, Ns, tw, tid, nthreads);
+            stockham_pass_inplace<T, 2, (E + 1) / 2>(buf, n, nb, fnb, Ns, fns, twl, tid, nthreads);
             break;
         case 3:
-            stockham_pass_inplace<T, 3, (E + 2) / 3>(buf, n, nb, Ns, tw, tid, nthreads);
+            stockham_pass_inplace<T, 3, (E + 2) / 3>(buf, n, nb, fnb, Ns, fns, twl, tid, nthreads);
             break;
         default:
-            stockham_pass_inplace<T, 5, (E + 4) / 5>(buf, n, nb, Ns, tw, tid, nthreads);
+            stockham_pass_inplace<T, 5, (E + 4) / 5>(buf, n, nb, fnb, Ns, fns, twl, tid, nthreads);
             break;
         }
         Ns *= R;

@@ -59,7 +59,7 @@ static fio_status build_state(MultiState &st, int n, const fio_plan_t *plans, co
     for (int i = 0; i < n; ++i) {
         const fio_plan_s *P = plans[i];
         for (const RowItem &r : P->rows)
-            rows.push_back(MultiRowItem{i, r.l, r.k1, r.t0, r.tn, 0});
+            rows.push_back(MultiRowItem{i, r.l, r.k1, r.nr, r.t0, r.tn});
         for (int b = 0; b < B[i]; ++b)
             for (const ColItem &c : P->cols)
                 cols.push_back(MultiColItem{i, c.l, c.tau0, c.nb, b, 0});

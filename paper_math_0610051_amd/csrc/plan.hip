@@ -815,20 +815,31 @@ static fio_status plan_layout(fio_plan_s *P) {
         H_off += (long long)W.B[0] * W.n[1] * W.qpad;
         D.G_off = G_off;
         G_off += (long long)W.n[0] * W.n[1] * W.qpad;
-        // stage-1 items: box rows, rank chunks fitting the LDS
+        // stage-1 items: nr adjacent box rows with all ranks when they fit the
+        // LDS buffer, else single rows in rank chunks
         const int tn = (int)std::max<long long>(1, std::min<long long>(W.qpad, cap / W.n[1]));
-        for (int k1 = 0; k1 < W.B[0]; ++k1)
+        const int nr = tn == W.qpad ? (int)std::max<long long>(1, std::min<long long>(W.B[0], cap / ((long long)W.n[1] * tn))) : 1;
+        for (int k1 = 0; k1 < W.B[0]; k1 += nr)
             for (int t0 = 0; t0 < W.qpad; t0 += tn)
-                P->rows.push_back(RowItem{l, k1, t0, std::min(tn, W.qpad - t0)});
-        lds_rows = std::max(lds_rows, (size_t)W.n[1] * tn * P->esize);
-        // stage-2 items: a power of two of adjacent transforms tau = j2 * q + t filling the buffer
-        const long long ntau = (long long)W.n[1] * W.qpad;
-        int nb = 1;
-        while (2LL * nb * W.n[0] <= cap && 2LL * nb <= ntau && nb < 64)
-            nb *= 2;
-        for (long long t0 = 0; t0 < ntau; t0 += nb)
-            P->cols.push_back(ColItem{l, (int)t0, (int)std::min<long long>(nb, ntau - t0), 0});
-        lds_cols = std::max(lds_cols, (size_t)W.n[0] * nb * P->esize);
+                P->rows.push_back(RowItem{l, k1, std::min(nr, W.B[0] - k1), t0, std::min(tn, W.qpad - t0), 0});
+        lds_rows = std::max(lds_rows, (size_t)W.n[1] * (nr * tn + 1) * P->esize);  // buffer + twiddles
+        // stage-2 items: whole cell columns (all ranks of ncol adjacent j2) when
+        // one column fits, else rank ranges of one column (a divisor of q)
+        const long long colsz = (long long)W.n[0] * W.qpad;
+        if (colsz <= cap) {
+            const int ncol = (int)std::min<long long>(W.n[1], cap / colsz);
+            for (int j2 = 0; j2 < W.n[1]; j2 += ncol)
+                P->cols.push_back(ColItem{l, j2 * W.qpad, std::min(ncol, W.n[1] - j2) * W.qpad, 0});
+            lds_cols = std::max(lds_cols, (size_t)(colsz * ncol + W.n[0]) * P->esize);  // buffer + twiddles
+        } else {
+            int nb = W.qpad;
+            while (nb > 1 && ((long long)nb * W.n[0] > cap || W.qpad % nb))
+                --nb;
+            for (int j2 = 0; j2 < W.n[1]; ++j2)
+                for (int t0 = 0; t0 < W.qpad; t0 += nb)
+                    P->cols.push_back(ColItem{l, j2 * W.qpad + t0, nb, 0});
+            lds_cols = std::max(lds_cols, (size_t)W.n[0] * (nb + 1) * P->esize);  // buffer + twiddles
+        }
     }
     P->row_first[P->L] = (int)P->rows.size();
     P->col_first[P->L] = (int)P->cols.size();
@@ -914,6 +925,12 @@ static fio_status plan_exact(fio_plan_s *P, const double2 *d_xcoef) {
             fio_status st = separate_wedge(P, l, d_xcoef, scr);
             if (st != FIO_OK)
                 return st;
+            // the verification retries tighten the threshold; an estimate
+            // still above the whole budget means the tolerance is out of reach
+            if (P->wedges[l].sep_err > P->tol)
+                return (set_error("wedge " + std::to_string(l) + ": separation error estimate " +
+                                  std::to_string(P->wedges[l].sep_err) + " exceeds tol"),
+                        FIO_EACCURACY);
         }
     }
     fio_status st = plan_layout(P);

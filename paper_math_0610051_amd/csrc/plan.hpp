@@ -31,13 +31,13 @@ struct WedgeDev {
     long long mem_off;   // member tables: centred Omega index per member
     long long gxi_off;   // gamma^xi (deconvolved, 1/N folded in), nmem * q complex
     long long gx_off;    // gamma^x, N^2 * q complex
-    long long H_off;     // per-RHS row-transformed box, B1 * n2 * q complex
-    long long G_off;     // per-RHS oversampled grid, n1 * n2 * q complex
+    long long H_off;     // per-RHS row-transformed box, [j2][k1][rank]: n2 * B1 * q complex
+    long long G_off;     // per-RHS oversampled grid, [j2][j1][rank]: n2 * n1 * q complex
 };
 
 // Work items of the two FFT stages.
-struct RowItem {   // stage 1: one box row k1 of wedge ell, ranks [t0, t0 + tn)
-    int l, k1, t0, tn;
+struct RowItem {   // stage 1: box rows [k1, k1 + nr) of wedge ell, ranks [t0, t0 + tn)
+    int l, k1, nr, t0, tn, pad;
 };
 struct ColItem {   // stage 2: transforms tau in [tau0, tau0 + nb) of wedge ell (tau = j2 * q + t)
     int l, tau0, nb, pad;

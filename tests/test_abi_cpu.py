@@ -95,6 +95,7 @@ def _plan_status(N=64, kind=2, tol=1e-4, amp_kind=0, **opts):
     (dict(tol=1.5), fio.FIO_EINVAL),
     (dict(amp_kind=1), fio.FIO_ENOTSUP),
     (dict(tol=1e-8), fio.FIO_ENOTSUP),
+    (dict(tol=3e-7, precision=1), fio.FIO_ENOTSUP),
     (dict(precision=7), fio.FIO_EINVAL),
     (dict(partition=3), fio.FIO_EINVAL),
     (dict(max_batch=0), fio.FIO_EINVAL),

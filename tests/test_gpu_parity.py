@@ -283,6 +283,29 @@ def test_large_sizes_sampled(N, B):
     assert err <= 1e-4
 
 
+def test_fp64_long_columns_in_rank_chunks():
+    """FP64 at a tight tolerance: when a grid column of all ranks exceeds the
+    LDS transform buffer (n1 * qpad > 4096 complex doubles), the column stage
+    transforms it in rank chunks.  The result must still meet the tolerance."""
+    N, tol = 512, 1e-6
+    rng = fi.rng_for(1, 7)
+    fh = fi.fhat_from_f(fi.complex_gaussian(N, rng))
+    xs = fi.sample_points(N, 512, rng)
+    p = _plan(N, "c1c2", (1.0,), tol, precision="f64")
+    chunked = 0
+    for ell in range(p.L):
+        wi = p.wedge_info(ell)
+        qpad = wi["rank"] + (wi["rank"] & 1)
+        chunked += wi["rank"] > 0 and wi["fine"][0] * qpad > 4096
+    print("  wedges with rank-chunked columns: %d of %d; %s" % (chunked, p.L, p.info()))
+    assert chunked > 0
+    u = _apply(p, fh, "f64").ravel()[xs]
+    exact = od.direct(N, 2, (1.0,), fh, xs)
+    err = ref.rel_l2(u, exact)
+    print("  rel-l2 %.3e" % err)
+    assert err <= tol
+
+
 # ------------------------------------------------------------------ fused multi-instance launch (HIP graph)
 def test_multi_graph_replays_match_eager_results():
     """The captured graph is replayed several times with eager work in between;
