@@ -30,7 +30,7 @@ namespace fio {
 template <typename T>
 __device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it, const cplx<T> *__restrict__ fhat,
                                           long long fstride, int B) {
-    constexpr int E = kFftLdsBytes / (int)sizeof(cplx<T>) / kFftThreads;
+    constexpr int E = kRowLdsBytes / (int)sizeof(cplx<T>) / kFftThreads;
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
     const WedgeDev &W = a.wedges[it.l];
@@ -40,17 +40,61 @@ __device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it
     cplx<T> *twl = buf + n * nbt;  // the n twiddles follow the transform buffer
     for (int i = tid; i < n; i += nt)
         twl[i] = a.tw[W.tw2 + i];
-    const FastDiv ftn((unsigned)tn), fb2((unsigned)B2), fnbt((unsigned)nbt);
+    const FastDiv &ftn = it.ftn, &fb2 = W.fB2, &fnbt = it.fnbt;
     const int *map = a.map + W.map_off + (long long)it.k1 * B2;
     const int *omega = a.omega + W.mem_off;
     const cplx<T> *gxi = a.gxi + W.gxi_off + it.t0;
+    // This thread's box cells (row r, box column k2, rank t; rank fastest):
+    // buffer position, input index and frequency factor do not depend on
+    // the right-hand side, so they are looked up once for the whole batch.
+    // (cells beyond KR * nt, possible only for oversampling below 2, are
+    // looked up per right-hand side)
+    constexpr int KR = (E + 1) / 2;
+    int dst[KR], fidx[KR];
+    cplx<T> g[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int i = tid + k * nt;
+        dst[k] = -1;
+        fidx[k] = 0;
+        g[k] = cmake<T>(0, 0);
+        if (i < nr * B2 * tn) {
+            const int rk = ftn.div(i), t = i - rk * tn;
+            const int r = fb2.div(rk), k2 = rk - r * B2;
+            const int m = map[r * B2 + k2];
+            if (m >= 0) {
+                int j2 = lo2 + k2;
+                if (j2 < 0)
+                    j2 += n;
+                dst[k] = j2 * nbt + r * tn + t;
+                fidx[k] = omega[m];
+                g[k] = gxi[(long long)m * q + t];
+            }
+        }
+    }
+    // this thread's inputs of the next right-hand side, fetched during the
+    // current one's transform
+    cplx<T> fv[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k)
+        if (dst[k] >= 0)
+            fv[k] = fhat[fidx[k]];
     for (int b = 0; b < B; ++b) {
         for (int i = tid; i < n * nbt; i += nt)
             buf[i] = cmake<T>(0, 0);
         __syncthreads();
         const cplx<T> *f = fhat + b * fstride;
-        // (row r, box column k2, rank t), rank fastest
-        for (int i = tid; i < nr * B2 * tn; i += nt) {
+#pragma unroll
+        for (int k = 0; k < KR; ++k)
+            if (dst[k] >= 0)
+                buf[dst[k]] = cmul(fv[k], g[k]);
+        if (b + 1 < B) {
+#pragma unroll
+            for (int k = 0; k < KR; ++k)
+                if (dst[k] >= 0)
+                    fv[k] = f[fstride + fidx[k]];
+        }
+        for (int i = tid + KR * nt; i < nr * B2 * tn; i += nt) {
             const int rk = ftn.div(i), t = i - rk * tn;
             const int r = fb2.div(rk), k2 = rk - r * B2;
             const int m = map[r * B2 + k2];
@@ -84,19 +128,21 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kFf
                                                             const MultiRowItem *__restrict__ items) {
     const MultiRowItem m = items[blockIdx.x];
     const InstArgs<T> &I = inst[m.inst];
-    rows_body<T>(I.a, RowItem{m.l, m.k1, m.nr, m.t0, m.tn, 0}, I.fhat, (long long)I.a.N * I.a.N, I.B);
+    rows_body<T>(I.a, m.it, I.fhat, (long long)I.a.N * I.a.N, I.B);
 }
 
 // ---------------------------------------------------------------------------
 // Stage 2: FFT along axis 1 (length n1, the long side) of nb transforms
-// tau = j2 * q + t, tau0 <= tau < tau0 + nb; rows outside the box are the
-// implicit zero padding.  Items hold whole cell columns (nb a multiple of q,
-// tau0 aligned) or a rank range of one column.  With H [j2][k1][rank] and
-// G [j2][j1][rank] a whole-column item reads and writes contiguous runs.
+// tau = j2 * q + t, tau0 <= tau < tau0 + nb, of right-hand side b; rows
+// outside the box are the implicit zero padding.  Items hold whole cell
+// columns (nb a multiple of q, tau0 aligned) or a rank range of one column.
+// With H [j2][k1][rank] and G [j2][j1][rank] a whole-column item reads and
+// writes contiguous runs.  Many small workgroups per CU overlap one another's
+// load, transform and store phases.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it, int b) {
-    constexpr int E = kFftLdsBytes / (int)sizeof(cplx<T>) / kFftThreads;
+    constexpr int E = kColLdsBytes / (int)sizeof(cplx<T>) / kColThreads;
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
     const WedgeDev &W = a.wedges[it.l];
@@ -106,14 +152,14 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
     cplx<T> *twl = buf + n * nb;  // the n twiddles follow the transform buffer
     for (int i = tid; i < n; i += nt)
         twl[i] = a.tw[W.tw1 + i];
-    for (int i = tid; i < n * nb; i += nt)
+    // padding rows j1 in [B1 - B1/2, n - B1/2) are zero
+    for (int i = (B1 - B1 / 2) * nb + tid; i < (n - B1 / 2) * nb; i += nt)
         buf[i] = cmake<T>(0, 0);
-    const FastDiv fnb((unsigned)nb), fq((unsigned)q), fb1((unsigned)B1), fn((unsigned)n);
-    __syncthreads();
-    const cplx<T> *H = a.H + b * a.H_stride + W.H_off;
-    cplx<T> *G = a.G + b * a.G_stride + W.G_off;
+    const FastDiv &fnb = it.fnb, &fq = W.fq, &fb1 = W.fB1, &fn = W.fn1;
+    const cplx<T> *H = a.H + (long long)b * a.H_stride + W.H_off;
+    cplx<T> *G = a.G + (long long)b * a.G_stride + W.G_off;
     const bool whole = nb >= q;  // whole columns: tau0 = j2_0 * q, nb = ncol * q
-    const int j20 = it.tau0 / q, t0 = it.tau0 - j20 * q;
+    const int j20 = fq.div(it.tau0), t0 = it.tau0 - j20 * q;
     if (whole) {
         // flat i = (col * B1 + k1) * q + t over the columns' contiguous runs
         const cplx<T> *src = H + (long long)it.tau0 * B1;
@@ -152,15 +198,16 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
 }
 
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kFftWavesPerEU))) void k_cols(PlanArgs<T> a, const ColItem *__restrict__ items) {
+__global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(kFftWavesPerEU))) void k_cols(
+    PlanArgs<T> a, const ColItem *__restrict__ items) {
     cols_body<T>(a, items[blockIdx.x], blockIdx.y);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kFftWavesPerEU))) void k_cols_multi(const InstArgs<T> *__restrict__ inst,
-                                                            const MultiColItem *__restrict__ items) {
+__global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(kFftWavesPerEU))) void k_cols_multi(
+    const InstArgs<T> *__restrict__ inst, const MultiColItem *__restrict__ items) {
     const MultiColItem m = items[blockIdx.x];
-    cols_body<T>(inst[m.inst].a, ColItem{m.l, m.tau0, m.nb, 0}, m.b);
+    cols_body<T>(inst[m.inst].a, m.it, m.b);
 }
 
 template <typename T>
@@ -383,20 +430,28 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         if (staged) {
             // source offsets (complex, rank 0) and window positions of this
             // thread's cells, in column-major cell order (G is [j2][j1][rank])
+            // J1 > -W and J1 + F1 <= 2 m1 (likewise for axis 2), so one
+            // conditional wrap brings every window cell onto the grid
             int off[kOff], dst[kOff];
-            int c0 = J2 % m2;
-            if (c0 < 0)
-                c0 += m2;
+            const int c0 = J2 < 0 ? J2 + m2 : (J2 >= m2 ? J2 - m2 : J2);
+            const int r0 = J1 < 0 ? J1 + m1 : (J1 >= m1 ? J1 - m1 : J1);
+            const float rF1 = 1.0f / (float)F1;
 #pragma unroll
             for (int k = 0; k < kOff; ++k) {
                 const int e = tid + k * kThreads;
                 off[k] = -1;
                 dst[k] = 0;
                 if (e < F1 * F2) {
-                    const int cc = e / F1, rr = e - cc * F1;
-                    int gr = (J1 + rr) % m1;
-                    if (gr < 0)
-                        gr += m1;
+                    // e / F1 for e < 2^11: the float quotient is off by at most one
+                    int cc = (int)((float)e * rF1);
+                    if (cc * F1 > e)
+                        --cc;
+                    else if ((cc + 1) * F1 <= e)
+                        ++cc;
+                    const int rr = e - cc * F1;
+                    int gr = r0 + rr;
+                    if (gr >= m1)
+                        gr -= m1;
                     int gc = c0 + cc;
                     if (gc >= m2)
                         gc -= m2;
@@ -635,7 +690,7 @@ static hipError_t apply_t(fio_plan_s *P, int B, const void *fhat, void *u, hipSt
         }
         if (c1 > c0) {
             StageTimer tm(P, 1, s);
-            k_cols<T><<<dim3(c1 - c0, bc), kFftThreads, P->lds_cols, s>>>(a, P->d_cols + c0);
+            k_cols<T><<<dim3(c1 - c0, bc), kColThreads, P->lds_cols, s>>>(a, P->d_cols + c0);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess)
                 return e;
@@ -680,7 +735,7 @@ static void launch_multi_w(const MultiLaunch &ml, hipStream_t s) {
     if (ml.nrows)
         k_rows_multi<T><<<ml.nrows, kFftThreads, ml.lds_rows, s>>>(I, ml.rows);
     if (ml.ncols)
-        k_cols_multi<T><<<ml.ncols, kFftThreads, ml.lds_cols, s>>>(I, ml.cols);
+        k_cols_multi<T><<<ml.ncols, kColThreads, ml.lds_cols, s>>>(I, ml.cols);
     if (ml.ntiles)
         k_interp_multi<T, W><<<ml.ntiles, kThreads, kInterpLdsBytes, s>>>(I, ml.tiles);
 }

@@ -14,7 +14,9 @@ constexpr int kInterpLdsBytes = 32768;  // LDS window of one wedge's grid per in
 constexpr int kMaxLdsBytes = 131072;  // largest dynamic LDS request of any apply kernel
 constexpr int kFftThreads = 512;     // workgroup size of the two FFT stages
 constexpr int kFftWavesPerEU = 4;    // register budget: two FFT workgroups per CU overlap load, transform and store
-constexpr int kFftLdsBytes = 32768;   // in-place FFT buffer of one workgroup (two workgroups per CU)
+constexpr int kRowLdsBytes = 32768;   // in-place FFT buffer of a row-stage workgroup
+constexpr int kColLdsBytes = 32768;   // in-place FFT buffer of a column-stage workgroup
+constexpr int kColThreads = 512;      // workgroup size of the column stage
 constexpr int kInterpWidths[] = {4, 5, 6, 7, 8, 10, 12, 14, 16};
 
 // Per-instance arguments of the multi-instance kernels.
@@ -26,10 +28,12 @@ struct InstArgs {
     int B;
 };
 struct MultiRowItem {
-    int inst, l, k1, nr, t0, tn;
+    int inst;
+    RowItem it;
 };
-struct MultiColItem {
-    int inst, l, tau0, nb, b, pad;
+struct MultiColItem {  // one column item of one instance and right-hand side
+    int inst, b;
+    ColItem it;
 };
 struct MultiTile {
     int inst, tile, b0, nb;

@@ -19,6 +19,7 @@ struct FftPlan {
     int n;
     int npass;
     int radix[kMaxPasses];
+    int tfac[kMaxPasses];  // n / (Ns radix[p]): twiddle stride per unit of k
     FastDiv ns[kMaxPasses];
 };
 
@@ -51,6 +52,7 @@ inline bool fft_make_plan(int n, FftPlan &pl) {
     int Ns = 1;
     for (int p = 0; p < pl.npass; ++p) {
         pl.ns[p] = FastDiv((unsigned)Ns);
+        pl.tfac[p] = n / (Ns * pl.radix[p]);
         Ns *= pl.radix[p];
     }
     return m == 1;
@@ -183,11 +185,10 @@ __host__ __device__ inline void dft_small<double, 5>(cplx<double> *v) { dft5(v);
 // twl: the n twiddles W^i, i < n, in LDS.
 template <typename T, int R, int KB>
 __device__ __forceinline__ void stockham_pass_inplace(cplx<T> *buf, int n, int nb, const FastDiv &fnb, int Ns,
-                                                      const FastDiv &fns, const cplx<T> *twl, int tid,
+                                                      const FastDiv &fns, int tfac, const cplx<T> *twl, int tid,
                                                       int nthreads) {
     const int m = n / R;
     const int total = m * nb;
-    const int tfac = m / Ns;  // n / (Ns R)
     cplx<T> v[KB][R];
     int dst[KB];
 #pragma unroll
@@ -228,21 +229,22 @@ __device__ __forceinline__ void fft_inplace(cplx<T> *buf, const FftPlan *pl, int
     for (int p = 0; p < npass; ++p) {
         const int R = pl->radix[p];
         const FastDiv fns = pl->ns[p];
+        const int tfac = pl->tfac[p];
         switch (R) {
         case 8:
-            stockham_pass_inplace<T, 8, (E + 7) / 8>(buf, n, nb, fnb, Ns, fns, twl, tid, nthreads);
+            stockham_pass_inplace<T, 8, (E + 7) / 8>(buf, n, nb, fnb, Ns, fns, tfac, twl, tid, nthreads);
             break;
         case 4:
-            stockham_pass_inplace<T, 4, (E + 3) / 4>(buf, n, nb, fnb, Ns, fns, twl, tid, nthreads);
+            stockham_pass_inplace<T, 4, (E + 3) / 4>(buf, n, nb, fnb, Ns, fns, tfac, twl, tid, nthreads);
             break;
         case 2:
-            stockham_pass_inplace<T, 2, (E + 1) / 2>(buf, n, nb, fnb, Ns, fns, twl, tid, nthreads);
+            stockham_pass_inplace<T, 2, (E + 1) / 2>(buf, n, nb, fnb, Ns, fns, tfac, twl, tid, nthreads);
             break;
         case 3:
-            stockham_pass_inplace<T, 3, (E + 2) / 3>(buf, n, nb, fnb, Ns, fns, twl, tid, nthreads);
+            stockham_pass_inplace<T, 3, (E + 2) / 3>(buf, n, nb, fnb, Ns, fns, tfac, twl, tid, nthreads);
             break;
         default:
-            stockham_pass_inplace<T, 5, (E + 4) / 5>(buf, n, nb, fnb, Ns, fns, twl, tid, nthreads);
+            stockham_pass_inplace<T, 5, (E + 4) / 5>(buf, n, nb, fnb, Ns, fns, tfac, twl, tid, nthreads);
             break;
         }
         Ns *= R;

@@ -59,10 +59,10 @@ static fio_status build_state(MultiState &st, int n, const fio_plan_t *plans, co
     for (int i = 0; i < n; ++i) {
         const fio_plan_s *P = plans[i];
         for (const RowItem &r : P->rows)
-            rows.push_back(MultiRowItem{i, r.l, r.k1, r.nr, r.t0, r.tn});
+            rows.push_back(MultiRowItem{i, r});
         for (int b = 0; b < B[i]; ++b)
             for (const ColItem &c : P->cols)
-                cols.push_back(MultiColItem{i, c.l, c.tau0, c.nb, b, 0});
+                cols.push_back(MultiColItem{i, b, c});
         const int t = (P->N + kTileX - 1) / kTileX;
         for (int k = 0; k < t * t; ++k)
             tiles.push_back(MultiTile{i, k, 0, B[i]});

@@ -761,7 +761,8 @@ static fio_status plan_layout(fio_plan_s *P) {
     const long long NN = (long long)N * N;
     const int h = N / 2;
     P->esize = P->precision == FIO_F64 ? 16 : 8;
-    const long long cap = kFftLdsBytes / (long long)P->esize;  // complex elements of the in-place FFT buffer
+    // complex elements of the in-place FFT buffers of the row and column stages
+    const long long cap = kRowLdsBytes / (long long)P->esize, capc = kColLdsBytes / (long long)P->esize;
     P->qmax = 0;
     P->wdev.assign(P->L, WedgeDev());
     P->rows.clear();
@@ -796,12 +797,17 @@ static fio_status plan_layout(fio_plan_s *P) {
         D.lo1 = W.lo[0];
         D.lo2 = W.lo[1];
         D.q = W.qpad;
+        D.fq = FastDiv((unsigned)std::max(1, W.qpad));
+        D.fB1 = FastDiv((unsigned)W.B[0]);
+        D.fB2 = FastDiv((unsigned)W.B[1]);
+        D.fn1 = FastDiv((unsigned)W.n[0]);
+        D.fn2 = FastDiv((unsigned)W.n[1]);
         D.nmem = (int)W.members.size();
         D.fft1 = W.fft[0];
         D.fft2 = W.fft[1];
         D.tw1 = P->tw_off[D.fft1];
         D.tw2 = P->tw_off[D.fft2];
-        if (W.n[0] > cap || W.n[1] > cap)
+        if (W.n[0] > capc || W.n[1] > cap)
             return (set_error("oversampled grid too long for the LDS transform"), FIO_ENOTSUP);
         D.map_off = map_off;
         map_off += (long long)W.B[0] * W.B[1];
@@ -821,23 +827,23 @@ static fio_status plan_layout(fio_plan_s *P) {
         const int nr = tn == W.qpad ? (int)std::max<long long>(1, std::min<long long>(W.B[0], cap / ((long long)W.n[1] * tn))) : 1;
         for (int k1 = 0; k1 < W.B[0]; k1 += nr)
             for (int t0 = 0; t0 < W.qpad; t0 += tn)
-                P->rows.push_back(RowItem{l, k1, std::min(nr, W.B[0] - k1), t0, std::min(tn, W.qpad - t0), 0});
+                P->rows.push_back(make_row_item(l, k1, std::min(nr, W.B[0] - k1), t0, std::min(tn, W.qpad - t0)));
         lds_rows = std::max(lds_rows, (size_t)W.n[1] * (nr * tn + 1) * P->esize);  // buffer + twiddles
         // stage-2 items: whole cell columns (all ranks of ncol adjacent j2) when
         // one column fits, else rank ranges of one column (a divisor of q)
         const long long colsz = (long long)W.n[0] * W.qpad;
-        if (colsz <= cap) {
-            const int ncol = (int)std::min<long long>(W.n[1], cap / colsz);
+        if (colsz <= capc) {
+            const int ncol = (int)std::min<long long>(W.n[1], capc / colsz);
             for (int j2 = 0; j2 < W.n[1]; j2 += ncol)
-                P->cols.push_back(ColItem{l, j2 * W.qpad, std::min(ncol, W.n[1] - j2) * W.qpad, 0});
+                P->cols.push_back(make_col_item(l, j2 * W.qpad, std::min(ncol, W.n[1] - j2) * W.qpad));
             lds_cols = std::max(lds_cols, (size_t)(colsz * ncol + W.n[0]) * P->esize);  // buffer + twiddles
         } else {
             int nb = W.qpad;
-            while (nb > 1 && ((long long)nb * W.n[0] > cap || W.qpad % nb))
+            while (nb > 1 && ((long long)nb * W.n[0] > capc || W.qpad % nb))
                 --nb;
             for (int j2 = 0; j2 < W.n[1]; ++j2)
                 for (int t0 = 0; t0 < W.qpad; t0 += nb)
-                    P->cols.push_back(ColItem{l, j2 * W.qpad + t0, nb, 0});
+                    P->cols.push_back(make_col_item(l, j2 * W.qpad + t0, nb));
             lds_cols = std::max(lds_cols, (size_t)W.n[0] * (nb + 1) * P->esize);  // buffer + twiddles
         }
     }

@@ -283,6 +283,24 @@ def test_large_sizes_sampled(N, B):
     assert err <= 1e-4
 
 
+@pytest.mark.parametrize("sigma", [1.5, 2.5])
+def test_other_oversampling_factors_full_grid(sigma):
+    """Oversampling other than 2: below 2 a box fills more than half of its
+    grid rows (the row stage then looks up part of its cells per right-hand
+    side); above 2 the grids grow.  Both must meet the tolerance."""
+    N, tol = 128, 1e-3
+    rng = fi.rng_for(1, 3)
+    fh = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=2))
+    p = _plan(N, "c1c2", (1.0,), tol, sigma=sigma)
+    u = p.apply(_dev(fh))
+    torch.cuda.synchronize()
+    u = u.cpu().numpy().astype(np.complex128).reshape(2, N * N)
+    exact = od.direct(N, 2, (1.0,), fh, np.arange(N * N))
+    err = ref.rel_l2(u, exact)
+    print("  sigma %.2f: kernel width %d, rel-l2 %.3e" % (sigma, p.info()["kernel_width"], err))
+    assert err <= tol
+
+
 def test_fp64_long_columns_in_rank_chunks():
     """FP64 at a tight tolerance: when a grid column of all ranks exceeds the
     LDS transform buffer (n1 * qpad > 4096 complex doubles), the column stage
