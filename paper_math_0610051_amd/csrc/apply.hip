@@ -340,13 +340,30 @@ __device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int l
     return F2 + best;
 }
 
+// acc[vb] += mod * v, without floating-point contraction, so that every call
+// site rounds alike (a batch then equals a loop of single right-hand sides bit
+// for bit).
+template <typename T>
+__device__ __forceinline__ void flush_rhs(cplx<T> (&acc)[kInterpBatch], int vb, const cplx<T> &mod,
+                                          const cplx<T> &v) {
+#pragma clang fp contract(off)
+    const T re = mod.re * v.re - mod.im * v.im;
+    const T im = mod.re * v.im + mod.im * v.re;
+#pragma unroll
+    for (int bb = 0; bb < kInterpBatch; ++bb)
+        if (bb == vb) {
+            acc[bb].re += re;
+            acc[bb].im += im;
+        }
+}
+
 template <typename T, int W>
 __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__restrict__ u, long long ustride, int B,
                                             int bofs, int l0, int l1, int tile) {
     using U = typename Unit16<T>::type;
     constexpr int CPU = 16 / (int)sizeof(cplx<T>);  // complex per 16-byte unit (rank pair / single rank)
     constexpr int kUnits = kInterpLdsBytes / 16;     // window capacity in units
-    constexpr int kOff = kUnits / kThreads;          // staged units of one plane per thread
+    constexpr int kOff = 6;                          // staged cells per thread: windows up to 1536 cells
     extern __shared__ unsigned char smem_raw[];
     U *win = reinterpret_cast<U *>(smem_raw);
     __shared__ double red[kThreads / 64][4];
@@ -423,7 +440,7 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         const int S2 = pick_row_stride(active, j1 - J1, j2 - J2, F2, lane, wave, red2);
         const int plane = F1 * S2;               // units of one rank-pair plane of the window
         const int ppr = kUnits / plane;          // planes staged per round
-        const bool staged = ppr >= 1 && F1 <= m1 && F2 <= m2;
+        const bool staged = ppr >= 1 && F1 <= m1 && F2 <= m2 && F1 * F2 <= kOff * kThreads;
         const cplx<T> *gxp = a.gx + wd.gx_off + p * q;
         const cplx<T> mod = cmake(cs, sn);
         const cplx<T> *G0 = a.G + (long long)bofs * a.G_stride + wd.G_off;
@@ -460,70 +477,89 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                 }
             }
             const int base = (j1 - J1) * S2 + (j2 - J2);
-            for (int b = 0; b < B; ++b) {
-                const cplx<T> *G = G0 + (long long)b * a.G_stride;
-                cplx<T> v = cmake<T>(0, 0);
-                for (int tu0 = 0; tu0 < qu; tu0 += ppr) {
-                    const int nt = min(ppr, qu - tu0);
-                    for (int tl = 0; tl < nt; ++tl) {
-                        const int tsrc = (tu0 + tl) * CPU;
+            // Planes (b, tl), right-hand side major, are staged ppr at a time, so
+            // one round serves several right-hand sides between two barriers.
+            const int nplanes = B * qu;
+            int pb = 0, ptl = 0;         // (b, tl) of the round's first plane
+            cplx<T> v = cmake<T>(0, 0);  // partial sum of right-hand side vb
+            int vb = 0;
+            for (int p0 = 0; p0 < nplanes; p0 += ppr) {
+                const int np = min(ppr, nplanes - p0);
+                {
+                    int b = pb, tl = ptl;
+                    for (int k2 = 0; k2 < np; ++k2) {
+                        const cplx<T> *G = G0 + (long long)b * a.G_stride + tl * CPU;
 #pragma unroll
                         for (int k = 0; k < kOff; ++k)
                             if (off[k] >= 0)
-                                win[tl * plane + dst[k]] = *reinterpret_cast<const U *>(G + off[k] + tsrc);
-                    }
-                    __syncthreads();
-                    if (active) {
-                        for (int tl = 0; tl < nt; ++tl) {
-                            const U *pw = win + tl * plane + base;
-                            U sum;
-                            if constexpr (CPU == 2)
-                                sum = make_float4(0.f, 0.f, 0.f, 0.f);
-                            else
-                                sum = make_double2(0.0, 0.0);
-#pragma unroll
-                            for (int i1 = 0; i1 < W; ++i1) {
-                                const U *pr = pw + i1 * S2;
-                                U rs = pr[0];
-                                rs.x *= w2[0];
-                                rs.y *= w2[0];
-                                if constexpr (CPU == 2) {
-                                    rs.z *= w2[0];
-                                    rs.w *= w2[0];
-                                }
-#pragma unroll
-                                for (int i2 = 1; i2 < W; ++i2) {
-                                    const U g = pr[i2];
-                                    rs.x += w2[i2] * g.x;
-                                    rs.y += w2[i2] * g.y;
-                                    if constexpr (CPU == 2) {
-                                        rs.z += w2[i2] * g.z;
-                                        rs.w += w2[i2] * g.w;
-                                    }
-                                }
-                                sum.x += w1[i1] * rs.x;
-                                sum.y += w1[i1] * rs.y;
-                                if constexpr (CPU == 2) {
-                                    sum.z += w1[i1] * rs.z;
-                                    sum.w += w1[i1] * rs.w;
-                                }
-                            }
-                            const U gx = *reinterpret_cast<const U *>(gxp + (tu0 + tl) * CPU);
-                            cfma(v, cmake<T>(gx.x, gx.y), cmake<T>(sum.x, sum.y));
-                            if constexpr (CPU == 2)
-                                cfma(v, cmake<T>(gx.z, gx.w), cmake<T>(sum.z, sum.w));
+                                win[k2 * plane + dst[k]] = *reinterpret_cast<const U *>(G + off[k]);
+                        if (++tl == qu) {
+                            tl = 0;
+                            ++b;
                         }
                     }
-                    __syncthreads();
                 }
-                const cplx<T> mv = cmul(mod, v);
+                __syncthreads();
+                if (active) {
+                    int b = pb, tl = ptl;
+                    for (int k2 = 0; k2 < np; ++k2) {
+                        if (b != vb) {
+                            flush_rhs<T>(acc, vb, mod, v);
+                            v = cmake<T>(0, 0);
+                            vb = b;
+                        }
+                        const U *pw = win + k2 * plane + base;
+                        U sum;
+                        if constexpr (CPU == 2)
+                            sum = make_float4(0.f, 0.f, 0.f, 0.f);
+                        else
+                            sum = make_double2(0.0, 0.0);
 #pragma unroll
-                for (int bb = 0; bb < kInterpBatch; ++bb)
-                    if (bb == b) {
-                        acc[bb].re += mv.re;
-                        acc[bb].im += mv.im;
+                        for (int i1 = 0; i1 < W; ++i1) {
+                            const U *pr = pw + i1 * S2;
+                            U rs = pr[0];
+                            rs.x *= w2[0];
+                            rs.y *= w2[0];
+                            if constexpr (CPU == 2) {
+                                rs.z *= w2[0];
+                                rs.w *= w2[0];
+                            }
+#pragma unroll
+                            for (int i2 = 1; i2 < W; ++i2) {
+                                const U g = pr[i2];
+                                rs.x += w2[i2] * g.x;
+                                rs.y += w2[i2] * g.y;
+                                if constexpr (CPU == 2) {
+                                    rs.z += w2[i2] * g.z;
+                                    rs.w += w2[i2] * g.w;
+                                }
+                            }
+                            sum.x += w1[i1] * rs.x;
+                            sum.y += w1[i1] * rs.y;
+                            if constexpr (CPU == 2) {
+                                sum.z += w1[i1] * rs.z;
+                                sum.w += w1[i1] * rs.w;
+                            }
+                        }
+                        const U gx = *reinterpret_cast<const U *>(gxp + tl * CPU);
+                        cfma(v, cmake<T>(gx.x, gx.y), cmake<T>(sum.x, sum.y));
+                        if constexpr (CPU == 2)
+                            cfma(v, cmake<T>(gx.z, gx.w), cmake<T>(sum.z, sum.w));
+                        if (++tl == qu) {
+                            tl = 0;
+                            ++b;
+                        }
                     }
+                }
+                ptl += np;
+                while (ptl >= qu) {
+                    ptl -= qu;
+                    ++pb;
+                }
+                __syncthreads();
             }
+            if (active)
+                flush_rhs<T>(acc, vb, mod, v);
         } else if (active) {
             // window too large for LDS (strongly folded warp): read the grid directly
             int g1i = j1 % m1, g2i = j2 % m2;
@@ -557,13 +593,7 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                     }
                     cfma(v, gxp[t], sum);
                 }
-                const cplx<T> mv = cmul(mod, v);
-#pragma unroll
-                for (int bb = 0; bb < kInterpBatch; ++bb)
-                    if (bb == b) {
-                        acc[bb].re += mv.re;
-                        acc[bb].im += mv.im;
-                    }
+                flush_rhs<T>(acc, b, mod, v);
             }
         }
     }

@@ -10,7 +10,7 @@ namespace fio {
 constexpr int kThreads = 256;       // workgroup size of every apply kernel
 constexpr int kInterpBatch = 8;     // right-hand sides per interpolation launch
 constexpr int kTileX = 16;          // interpolation tile: kTileX x kTileX output points per workgroup
-constexpr int kInterpLdsBytes = 32768;  // LDS window of one wedge's grid per interpolation workgroup
+constexpr int kInterpLdsBytes = 49152;  // LDS windows (rank planes of several right-hand sides) per interpolation workgroup
 constexpr int kMaxLdsBytes = 131072;  // largest dynamic LDS request of any apply kernel
 constexpr int kFftThreads = 512;     // workgroup size of the two FFT stages
 constexpr int kFftWavesPerEU = 4;    // register budget: two FFT workgroups per CU overlap load, transform and store
