@@ -296,7 +296,7 @@ def run_learned(args):
     net.generate(fi.training_scales(64), x_samples=args.learned_samples, r_cols=48)
     gen_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    loss = net.train(args.learned_steps, batch=8192, lr=2e-3, lr_final=1e-5)
+    loss = net.train(args.learned_steps, batch=args.learned_batch, lr=args.learned_lr, lr_final=1e-5)
     train_s = time.perf_counter() - t0
     held = fi.heldout_scales(16)
     net.generate(held, x_samples=1024, r_cols=48)
@@ -323,7 +323,8 @@ def run_learned(args):
             rows.append(dict(scale=float(s), tol=tol, learned_used=int(il["factor_mode"] == 3 and not il["fallback"]),
                              fallback=il["fallback"], learned_plan_s=learned_s, exact_plan_s=exact_s,
                              learned_applies_per_s=B * n / el, exact_applies_per_s=B * n / ee,
-                             learned_err=err_l, exact_err=err_e, learned_max_sep_err=il["max_sep_error"],
+                             learned_err=err_l, exact_err=err_e, learned_attempt_sep_err=il["learned_sep_error"],
+                             learned_attempt_ms=il["learned_ms"], plan_max_sep_err=il["max_sep_error"],
                              learned_factor_bytes=il["factor_bytes"], exact_compressed_bytes=ie["compressed_bytes"]))
             pl.close()
             pe.close()
@@ -350,9 +351,11 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the per-RHS loop comparison")
     ap.add_argument("--plan-params", default="", help="L,sigma,sep_tol_frac,nufft_tol_frac[,kernel_width] instead of autotuning")
     ap.add_argument("--traffic-record", default=os.path.join(ROOT, "profiles", "k_interp_traffic_N1024_B8_c1c2.json"))
-    ap.add_argument("--learned-steps", type=int, default=6000)
+    ap.add_argument("--learned-steps", type=int, default=150000)
     ap.add_argument("--learned-samples", type=int, default=4096)
     ap.add_argument("--learned-tol", type=float, default=1e-2)
+    ap.add_argument("--learned-batch", type=int, default=8192)
+    ap.add_argument("--learned-lr", type=float, default=2e-3)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -111,6 +111,8 @@ typedef struct {
     long long factor_bytes;    /* device bytes of stored factors */
     long long workspace_bytes; /* device bytes of the per-batch workspace */
     long long compressed_bytes;/* bytes of the compressed factors (V S^-1 and U_R^+, eq. (probnewfac)) */
+    double learned_sep_error;  /* largest separation-error estimate of the learned attempt (0: none) */
+    double learned_ms;         /* time of the learned attempt: inference, refit and estimate */
 } fio_plan_info_t;
 
 typedef struct {

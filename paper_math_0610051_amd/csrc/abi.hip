@@ -255,6 +255,8 @@ fio_status fio_plan_info(fio_plan_t P, fio_plan_info_t *o) {
     o->factor_bytes = P->factor_bytes;
     o->workspace_bytes = P->workspace_bytes;
     o->compressed_bytes = comp;
+    o->learned_sep_error = P->learned_sep_err;
+    o->learned_ms = P->learned_ms;
     return FIO_OK;
 }
 

@@ -1030,6 +1030,7 @@ static fio_status plan_learned(fio_plan_s *P, LearnedModel *net, const double2 *
         if (st != FIO_OK)
             return st;
         W.sep_err = separation_estimate(P, W, Gam, Del, UG);
+        P->learned_sep_err = std::max(P->learned_sep_err, W.sep_err);
         if (W.sep_err > target)
             *ok = false;
     }
@@ -1069,9 +1070,12 @@ fio_status build_plan(fio_plan_s *P) {
     }
     if (use_net) {
         bool ok = false;
+        const auto t_net = clock::now();
         st = plan_learned(P, net, d_xcoef, &ok);
         if (st != FIO_OK)
             return st;
+        FIO_HIP_TRY(hipDeviceSynchronize());
+        P->learned_ms = std::chrono::duration<double, std::milli>(clock::now() - t_net).count();
         if (!ok) {
             if (P->opt.factor_mode == FIO_FACTORS_LEARNED)
                 return (set_error("learned factors miss the error budget"), FIO_EACCURACY);

@@ -96,6 +96,7 @@ struct fio_plan_s {
     int qmax = 0;
     int fallback = 0, factor_mode = FIO_FACTORS_STORED;
     double plan_ms = 0;
+    double learned_sep_err = 0, learned_ms = 0;  // the learned attempt, if any
     std::vector<fio::WedgeHost> wedges;
     std::vector<int> wedge_of;   // N*N, centred
     std::vector<fio::WedgeDev> wdev;

@@ -52,7 +52,8 @@ class fio_plan_info_t(ctypes.Structure):
                 ("kernel_width", c_int), ("max_rank", c_int), ("min_rank", c_int), ("fallback", c_int),
                 ("sigma", c_double), ("tol", c_double), ("plan_ms", c_double), ("max_sep_error", c_double),
                 ("fine_cells", c_longlong), ("box_cells", c_longlong), ("factor_bytes", c_longlong),
-                ("workspace_bytes", c_longlong), ("compressed_bytes", c_longlong)]
+                ("workspace_bytes", c_longlong), ("compressed_bytes", c_longlong),
+                ("learned_sep_error", c_double), ("learned_ms", c_double)]
 
 
 class fio_tune_result_t(ctypes.Structure):

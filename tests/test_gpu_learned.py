@@ -112,3 +112,38 @@ def test_network_save_load_roundtrip(tmp_path):
     net.save(path)
     other = Learned.load(path)
     assert np.array_equal(net.params(), other.params())
+
+
+def test_trained_network_replaces_the_separation_on_heldout_scales():
+    """What the network gains: trained long enough on 16 phase scales, it
+    supplies the spatial factors of held-out scales at a 1e-2 budget with no
+    column sampling or eigen-decomposition (the plan does not fall back), the
+    apply meets the budget against the direct sum, and the plan's setup time
+    and the network's size are reported beside the exact separation's."""
+    from paper_math_0610051_amd import Learned, Plan
+    N, L, tol = 256, 16, 1e-2
+    net = Learned(N, "c1c2", (1.0,), n_wedges=L, seed=11)
+    net.generate(fi.training_scales(16), x_samples=2048, r_cols=48)
+    t0 = time.perf_counter()
+    net.train(60000, batch=4096, lr=2e-3, lr_final=1e-5)
+    train_s = time.perf_counter() - t0
+    rng = np.random.default_rng(12)
+    fhat = fi.fhat_from_f(fi.complex_gaussian(N, rng))
+    xs = fi.sample_points(N, 1024, rng)
+    used = 0
+    for s in fi.heldout_scales(4):
+        s = float(s)
+        pl = Plan(N, "c1c2", tol, params=(s,), n_wedges=L, learned=net, learned_scale=s)
+        pe = Plan(N, "c1c2", tol, params=(s,), n_wedges=L, factor_mode="stored")
+        il, ie = pl.info(), pe.info()
+        u = pl.apply(torch.from_numpy(fhat.astype(np.complex64)).cuda())
+        torch.cuda.synchronize()
+        exact = od.direct(N, 2, (s,), fhat, xs)
+        err = ref.rel_l2(u.cpu().numpy().ravel()[xs], exact)
+        print("  s=%.3f: learned used %d (attempt sep %.2e, %.0f ms) vs exact plan %.0f ms; err %.2e; "
+              "network %d B vs compressed exact factors %d B; training %.1f s"
+              % (s, 1 - il["fallback"], il["learned_sep_error"], il["learned_ms"], ie["plan_ms"], err,
+                 2 * Learned.param_count(), ie["compressed_bytes"], train_s))
+        assert err <= tol
+        used += il["fallback"] == 0 and il["factor_mode"] == 3
+    assert used >= 3
