@@ -9,6 +9,7 @@ tolerance split come from the library's autotuner (cached in
 $FIO_TUNE_CACHE, default /tmp/fio_tune_cache.txt).
 
 Other workloads (each prints its own JSON line):
+  --workload batch512 64 right-hand sides at N = 512 in one fused graph launch
   --workload uneven   32 instances, N in {128, ..., 1024}, one fused launch
   --workload learned  network-factor plan vs exact plan at N = 1024
 
@@ -235,6 +236,44 @@ def run_batched(args):
     print(json.dumps(res), flush=True)
 
 
+def run_batch512(args):
+    """64 right-hand sides at N = 512 under the c1/c2 phase in one fused graph launch."""
+    import numpy as np
+    import torch
+
+    import fio_inputs as fi
+    from paper_math_0610051_amd import Plan, apply_multi
+
+    N, B = 512, 64
+    t0 = time.perf_counter()
+    plan = Plan(N, "c1c2", args.tol, params=(1.0,), max_batch=B)
+    plan_s = time.perf_counter() - t0
+    rng = fi.rng_for(2, 0)
+    fh = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=B))
+    fd = torch.from_numpy(fh.astype(np.complex64)).cuda()
+    out = torch.empty_like(fd)
+    for _ in range(args.warmup):
+        apply_multi([plan], [fd], [out])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        apply_multi([plan], [fd], [out])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    errs = [plan.probe_error(fd[b], out[b], nsamples=32) for b in range(0, B, 8)]
+    info = plan.info()
+    res = dict(metric="FIO applies/s, N=512, 64 right-hand sides in one graph launch", value=B * args.steps / el,
+               unit="applies/s", n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * el / args.steps,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="c64 (fp32 data, fp64 phase)",
+               data="synthetic",
+               config=dict(workload="N=512 c1/c2 phase, B=64 complex-Gaussian right-hand sides, tol %g" % args.tol,
+                           wedges=info["L"], ranks=[info["min_rank"], info["max_rank"]],
+                           kernel_width=info["kernel_width"], plan_s=plan_s,
+                           workspace_gb=info["workspace_bytes"] / 1e9),
+               max_probe_rel_l2=max(errs), roofline=None, cpu_baseline=None)
+    print(json.dumps(res), flush=True)
+
+
 def run_uneven(args):
     import numpy as np
     import torch
@@ -342,7 +381,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("batched", "uneven", "learned"), default="batched")
+    ap.add_argument("--workload", choices=("batched", "batch512", "uneven", "learned"), default="batched")
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-4)
@@ -362,7 +401,8 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (the wedge sharding is described "
               "in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
-    {"batched": run_batched, "uneven": run_uneven, "learned": run_learned}[args.workload](args)
+    {"batched": run_batched, "batch512": run_batch512, "uneven": run_uneven,
+     "learned": run_learned}[args.workload](args)
 
 
 if __name__ == "__main__":

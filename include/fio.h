@@ -150,9 +150,11 @@ fio_status fio_apply_batch(fio_plan_t plan, int B, const void *fhat, void *u, vo
 
 /* n instances of possibly different N (each its own plan, all of one
  * precision), instance i with B[i] right-hand sides at fhat[i] -> u[i] (host
- * arrays of device pointers).  All instances and wedges run in one launch of
- * each stage; the launch sequence is captured into a HIP graph that is
- * replayed while the plans and pointers stay the same. */
+ * arrays of device pointers).  All instances, wedges and right-hand sides run
+ * in one launch of each stage; the launch sequence is captured into a HIP
+ * graph that is replayed while the plans and batch sizes stay the same (new
+ * pointers refresh its argument table).  Instances run one after another
+ * instead when their kernel widths differ or B[i] exceeds plan i's max_batch. */
 fio_status fio_apply_multi(int n, const fio_plan_t *plans, const void *const *fhat, void *const *u,
                            const int *B, void *stream);
 

@@ -63,9 +63,11 @@ static fio_status build_state(MultiState &st, int n, const fio_plan_t *plans, co
         for (int b = 0; b < B[i]; ++b)
             for (const ColItem &c : P->cols)
                 cols.push_back(MultiColItem{i, b, c});
+        // interpolation tiles in groups of up to kInterpBatch right-hand sides
         const int t = (P->N + kTileX - 1) / kTileX;
-        for (int k = 0; k < t * t; ++k)
-            tiles.push_back(MultiTile{i, k, 0, B[i]});
+        for (int b0 = 0; b0 < B[i]; b0 += kInterpBatch)
+            for (int k = 0; k < t * t; ++k)
+                tiles.push_back(MultiTile{i, k, b0, std::min(kInterpBatch, B[i] - b0)});
         lds_rows = std::max(lds_rows, P->lds_rows);
         lds_cols = std::max(lds_cols, P->lds_cols);
     }
@@ -110,7 +112,7 @@ fio_status multi_apply(int n, const fio_plan_t *plans, const void *const *fhat, 
                        hipStream_t s) {
     bool fused = true;
     for (int i = 0; i < n; ++i)
-        if (plans[i]->w != plans[0]->w || B[i] > plans[i]->bchunk || B[i] > kInterpBatch)
+        if (plans[i]->w != plans[0]->w || B[i] > plans[i]->bchunk)
             fused = false;
     if (!fused)
         return run_sequential(n, plans, fhat, u, B, s);

@@ -324,6 +324,28 @@ def test_fp64_long_columns_in_rank_chunks():
     assert err <= tol
 
 
+def test_batch_of_64_in_one_graph_at_512():
+    """64 complex-Gaussian right-hand sides at N = 512 in one fused graph
+    launch (all wedges, all right-hand sides): every input meets the budget
+    at sampled points, and the result equals the plain batched apply."""
+    from paper_math_0610051_amd import apply_multi
+    N, B, tol = 512, 64, 1e-4
+    rng = fi.rng_for(2, 0)
+    fh = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=B))
+    xs = fi.sample_points(N, 128, rng)
+    p = _plan(N, "c1c2", (1.0,), tol, max_batch=B)
+    fd = _dev(fh)
+    u = apply_multi([p], [fd])[0]
+    ub = p.apply(fd)
+    torch.cuda.synchronize()
+    assert torch.equal(u, ub)
+    got = u.cpu().numpy().astype(np.complex128).reshape(B, N * N)[:, xs]
+    exact = od.direct(N, 2, (1.0,), fh, xs)
+    errs = [ref.rel_l2(got[b], exact[b]) for b in range(B)]
+    print("  worst of %d inputs: rel-l2 %.3e" % (B, max(errs)))
+    assert max(errs) <= tol
+
+
 # ------------------------------------------------------------------ fused multi-instance launch (HIP graph)
 def test_multi_graph_replays_match_eager_results():
     """The captured graph is replayed several times with eager work in between;
