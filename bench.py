@@ -94,7 +94,7 @@ def cpu_baseline(N, phase_kind, params, fh, samples, seed):
         xs, ref
 
 
-def tuned_plan(N, tol, B, fixed=None):
+def tuned_plan(N, tol, B, fixed=None, factor_mode="auto"):
     """Plan with the autotuner's choice (cached on disk), or with fixed
     (n_wedges, sigma, sep_tol_frac, nufft_tol_frac) when given."""
     from paper_math_0610051_amd import Plan, autotune
@@ -110,7 +110,7 @@ def tuned_plan(N, tol, B, fixed=None):
     t0 = time.perf_counter()
     plan = Plan(N, "c1c2", tol, params=(1.0,), max_batch=B, n_wedges=best["n_wedges"], sigma=best["sigma"],
                 sep_tol_frac=best["sep_tol_frac"], nufft_tol_frac=best["nufft_tol_frac"],
-                kernel_width=best.get("kernel_width", 0))
+                kernel_width=best.get("kernel_width", 0), factor_mode=factor_mode)
     return plan, time.perf_counter() - t0, best
 
 
@@ -162,7 +162,7 @@ def run_batched(args):
     log("fio_copy: %.0f GB/s (read + write)" % copy_gbs)
     log("N=%d B=%d tol=%g: planning" % (N, B, args.tol))
     fixed = tuple(float(v) for v in args.plan_params.split(",")) if args.plan_params else None
-    plan, plan_s, best = tuned_plan(N, args.tol, B, fixed)
+    plan, plan_s, best = tuned_plan(N, args.tol, B, fixed, args.factor_mode)
     info = plan.info()
     rng = fi.rng_for(4, 0)
     fh = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=B))
@@ -218,11 +218,14 @@ def run_batched(args):
                steps=steps, warmup=args.warmup, ms_per_step=1e3 * elapsed / steps, higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="c64 (fp32 data, fp64 phase and points)", data="synthetic",
                config=dict(workload="N=%d c1/c2 ellipse phase (scale 1), B=%d complex-Gaussian right-hand sides, "
-                                    "tol %g, exact randomized-separation factors, %s" % (N, B, args.tol, "autotuned" if fixed is None else "fixed plan"),
+                                    "tol %g, exact randomized-separation factors (%s), %s"
+                                    % (N, B, args.tol, args.factor_mode if args.factor_mode != "auto" else "stored",
+                                       "autotuned" if fixed is None else "fixed plan"),
                            N=N, batch=B, tol=args.tol, wedges=info["L"], ranks=[info["min_rank"], info["max_rank"]],
                            kernel_width=info["kernel_width"], sigma=info["sigma"],
                            sep_tol_frac=best["sep_tol_frac"], nufft_tol_frac=best["nufft_tol_frac"],
-                           plan_s=plan_s, tuned=fixed is None, parallelism="single GPU"),
+                           plan_s=plan_s, tuned=fixed is None, factor_bytes=info["factor_bytes"],
+                           parallelism="single GPU"),
                roofline=roof, stages=stages,
                comparison=dict(per_rhs_loop_applies_per_s=single_value, batched_applies_per_s=value))
     if not args.no_cpu_baseline:
@@ -388,6 +391,8 @@ def main():
     ap.add_argument("--cpu-samples", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the per-RHS loop comparison")
+    ap.add_argument("--factor-mode", choices=("auto", "stored", "regen"), default="auto",
+                    help="batched workload: stored spatial factors or regenerated ones")
     ap.add_argument("--plan-params", default="", help="L,sigma,sep_tol_frac,nufft_tol_frac[,kernel_width] instead of autotuning")
     ap.add_argument("--traffic-record", default=os.path.join(ROOT, "profiles", "k_interp_traffic_N1024_B8_c1c2.json"))
     ap.add_argument("--learned-steps", type=int, default=150000)

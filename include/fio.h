@@ -82,7 +82,14 @@ typedef struct {
 
 enum { FIO_F32 = 0, FIO_F64 = 1 };
 enum { FIO_PART_EQUIANGULAR = 0, FIO_PART_CORONAE = 1 };
-enum { FIO_FACTORS_AUTO = 0, FIO_FACTORS_STORED = 1, FIO_FACTORS_LEARNED = 3 };
+/* Factor modes.  STORED keeps gamma^x for every grid point (N^2 q complex per
+ * wedge); REGEN keeps only the compressed factors of eq. (probnewfac), the
+ * sampled columns C and Z = V S^-1, and the apply recomputes
+ * gamma^x(x) = A(x, C) Z from the FP64 residual phase (Section 3.2, the
+ * storage-compressed form): far less memory, more arithmetic per apply, and
+ * available while the padded rank is at most 16 (FP32) or 8 (FP64);
+ * LEARNED takes gamma^x from a trained network. */
+enum { FIO_FACTORS_AUTO = 0, FIO_FACTORS_STORED = 1, FIO_FACTORS_REGEN = 2, FIO_FACTORS_LEARNED = 3 };
 
 /* Plan options.  Start from fio_default_options(); zero means "automatic" where noted. */
 typedef struct {
@@ -90,7 +97,7 @@ typedef struct {
                                FIO_F64: FP64 throughout */
     int partition;          /* FIO_PART_EQUIANGULAR (Section 1.3) or FIO_PART_CORONAE (dyadic rings) */
     int n_wedges;           /* equiangular wedge count L; 0 = 8 * ceil(sqrt(N) / 8) */
-    int factor_mode;        /* FIO_FACTORS_AUTO / STORED (exact separation) / LEARNED (network) */
+    int factor_mode;        /* FIO_FACTORS_AUTO / STORED / REGEN (exact separation) / LEARNED (network) */
     unsigned long long seed;/* seed of the column/row sampling of the separation */
     int max_batch;          /* right-hand sides processed per pass of the workspace (default 8) */
     double sep_tol_frac;    /* separation threshold = tol * sep_tol_frac (default 0.25) */

@@ -134,6 +134,8 @@ fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, 
     // 1e-7 of the largest (its threshold is tol * sep_tol_frac)
     if (tol < 5e-7)
         return (set_error("tol below the floor (5e-7) of the Gram-matrix separation"), FIO_ENOTSUP);
+    if (o.factor_mode < FIO_FACTORS_AUTO || o.factor_mode > FIO_FACTORS_LEARNED)
+        return (set_error("unknown factor mode"), FIO_EINVAL);
     if (o.factor_mode == FIO_FACTORS_LEARNED && !o.learned)
         return (set_error("FIO_FACTORS_LEARNED needs a trained network"), FIO_EINVAL);
     fio_plan_s *P = new (std::nothrow) fio_plan_s();
@@ -353,8 +355,23 @@ fio_status fio_wedge_factors(fio_plan_t P, int l, int nx, const long long *xidx,
             return err;
         return hipMemcpy(dst, d_out, sizeof(double2) * (size_t)n * q, hipMemcpyDeviceToHost);
     };
-    if (nx > 0)
+    if (nx > 0 && P->regen) {
+        // regenerated factors: gamma^x(x, t) = sum_c A(x, C_c) Z(c, t) in FP64 on the host
+        const double e1 = std::cos(W.theta), e2 = std::sin(W.theta);
+        for (int i = 0; i < nx; ++i)
+            for (int t = 0; t < q; ++t) {
+                zd acc(0, 0);
+                for (size_t c = 0; c < W.C.size(); ++c) {
+                    const int om = W.members[W.C[c]];
+                    acc += host_residual(P->phase, P->N, xidx[i], e1, e2, om / P->N - h, om % P->N - h) *
+                           W.Z[c * q + t];
+                }
+                gx[((size_t)i * q + t) * 2] = acc.real();
+                gx[((size_t)i * q + t) * 2 + 1] = acc.imag();
+            }
+    } else if (nx > 0) {
         e = run(xidx, nx, true, gx);
+    }
     if (e == hipSuccess && nxi > 0) {
         e = run(mrows.data(), nxi, false, gxi);
         for (int j = 0; j < nxi && e == hipSuccess; ++j)

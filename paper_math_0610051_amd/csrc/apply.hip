@@ -344,20 +344,20 @@ __device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int l
 // site rounds alike (a batch then equals a loop of single right-hand sides bit
 // for bit).
 template <typename T>
-__device__ __forceinline__ void flush_rhs(cplx<T> (&acc)[kInterpBatch], int vb, const cplx<T> &mod,
-                                          const cplx<T> &v) {
+__device__ __forceinline__ cplx<T> rotate_rhs(const cplx<T> &mod, const cplx<T> &v) {
 #pragma clang fp contract(off)
-    const T re = mod.re * v.re - mod.im * v.im;
-    const T im = mod.re * v.im + mod.im * v.re;
-#pragma unroll
-    for (int bb = 0; bb < kInterpBatch; ++bb)
-        if (bb == vb) {
-            acc[bb].re += re;
-            acc[bb].im += im;
-        }
+    return cmake<T>(mod.re * v.re - mod.im * v.im, mod.re * v.im + mod.im * v.re);
 }
+// acc[vb] += mv for a run-time vb, by predication over the registers of acc
+#define FIO_ACC_ADD(acc, vb, mv)                          \
+    do {                                                  \
+        _Pragma("unroll") for (int bb_ = 0; bb_ < kInterpBatch; ++bb_) if (bb_ == (vb)) { \
+            acc[bb_].re += (mv).re;                       \
+            acc[bb_].im += (mv).im;                       \
+        }                                                 \
+    } while (0)
 
-template <typename T, int W>
+template <typename T, int W, bool REGEN>
 __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__restrict__ u, long long ustride, int B,
                                             int bofs, int l0, int l1, int tile) {
     using U = typename Unit16<T>::type;
@@ -392,6 +392,40 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         const int m1 = wd.n1, m2 = wd.n2, q = wd.q, qu = q / CPU;
         double g1, g2;
         phase_grad(a.phase, c, wd.e1, wd.e2, g1, g2);
+        // FIO_FACTORS_REGEN: gamma^x(x, t) = sum_c A(x, C_c) Z(c, t) for this
+        // thread's point from the FP64 residual phase, into LDS after the
+        // window ([t / CPU][thread] units; each thread reads only its own)
+        cplx<T> *gxl = reinterpret_cast<cplx<T> *>(smem_raw + kInterpLdsBytes);
+        if constexpr (REGEN) {
+            const double2 *zc = a.zcol + wd.zc_off;
+            const double2 *zm = a.zmat + wd.zm_off;
+            constexpr int kC = 8;
+            for (int t0 = 0; t0 < q; t0 += kC) {
+                double ar[kC], ai[kC];
+#pragma unroll
+                for (int t = 0; t < kC; ++t)
+                    ar[t] = ai[t] = 0;
+                for (int cc = 0; cc < wd.zrc; ++cc) {
+                    const double2 k = zc[cc];
+                    double cs2, sn2;
+                    expi2pi(residual_reduced(a.phase, c, g1, g2, k.x, k.y), cs2, sn2);
+                    const double2 *zr = zm + (long long)cc * q + t0;
+#pragma unroll
+                    for (int t = 0; t < kC; ++t)
+                        if (t0 + t < q) {
+                            const double2 z = zr[t];
+                            ar[t] += cs2 * z.x - sn2 * z.y;
+                            ai[t] += cs2 * z.y + sn2 * z.x;
+                        }
+                }
+#pragma unroll
+                for (int t = 0; t < kC; ++t)
+                    if (t0 + t < q) {
+                        const int tt = t0 + t;
+                        gxl[((tt / CPU) * kThreads + tid) * CPU + tt % CPU] = cmake<T>((T)ar[t], (T)ai[t]);
+                    }
+            }
+        }
         const double y1 = x1 + g1, y2 = x2 + g2;
         const double yp1 = wd.mt[0] * y1 + wd.mt[1] * y2;
         const double yp2 = wd.mt[2] * y1 + wd.mt[3] * y2;
@@ -504,7 +538,8 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                     int b = pb, tl = ptl;
                     for (int k2 = 0; k2 < np; ++k2) {
                         if (b != vb) {
-                            flush_rhs<T>(acc, vb, mod, v);
+                            const cplx<T> mv = rotate_rhs<T>(mod, v);
+                            FIO_ACC_ADD(acc, vb, mv);
                             v = cmake<T>(0, 0);
                             vb = b;
                         }
@@ -541,7 +576,8 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                                 sum.w += w1[i1] * rs.w;
                             }
                         }
-                        const U gx = *reinterpret_cast<const U *>(gxp + tl * CPU);
+                        const U gx = REGEN ? reinterpret_cast<const U *>(gxl)[tl * kThreads + tid]
+                                           : *reinterpret_cast<const U *>(gxp + tl * CPU);
                         cfma(v, cmake<T>(gx.x, gx.y), cmake<T>(sum.x, sum.y));
                         if constexpr (CPU == 2)
                             cfma(v, cmake<T>(gx.z, gx.w), cmake<T>(sum.z, sum.w));
@@ -558,8 +594,10 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                 }
                 __syncthreads();
             }
-            if (active)
-                flush_rhs<T>(acc, vb, mod, v);
+            if (active) {
+                const cplx<T> mv = rotate_rhs<T>(mod, v);
+                FIO_ACC_ADD(acc, vb, mv);
+            }
         } else if (active) {
             // window too large for LDS (strongly folded warp): read the grid directly
             int g1i = j1 % m1, g2i = j2 % m2;
@@ -591,9 +629,10 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                         sum.re += w1[i1] * rs.re;
                         sum.im += w1[i1] * rs.im;
                     }
-                    cfma(v, gxp[t], sum);
+                    cfma(v, REGEN ? gxl[((t / CPU) * kThreads + tid) * CPU + t % CPU] : gxp[t], sum);
                 }
-                flush_rhs<T>(acc, b, mod, v);
+                const cplx<T> mv = rotate_rhs<T>(mod, v);
+                FIO_ACC_ADD(acc, b, mv);
             }
         }
     }
@@ -611,19 +650,19 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
 template <typename T>
 constexpr int kInterpWavesPerEU = sizeof(T) == 4 ? 3 : 1;
 
-template <typename T, int W>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T>))) void k_interp(PlanArgs<T> a, cplx<T> *__restrict__ u, long long ustride,
-                                                     int B, int bofs, int l0, int l1) {
-    interp_body<T, W>(a, u, ustride, B, bofs, l0, l1, blockIdx.x);
+template <typename T, int W, bool REGEN>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T>))) void k_interp(
+    PlanArgs<T> a, cplx<T> *__restrict__ u, long long ustride, int B, int bofs, int l0, int l1) {
+    interp_body<T, W, REGEN>(a, u, ustride, B, bofs, l0, l1, blockIdx.x);
 }
 
-template <typename T, int W>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T>))) void k_interp_multi(const InstArgs<T> *__restrict__ inst,
-                                                           const MultiTile *__restrict__ tiles) {
+template <typename T, int W, bool REGEN>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T>))) void k_interp_multi(
+    const InstArgs<T> *__restrict__ inst, const MultiTile *__restrict__ tiles) {
     const MultiTile m = tiles[blockIdx.x];
     const InstArgs<T> &I = inst[m.inst];
-    interp_body<T, W>(I.a, I.u + (long long)m.b0 * I.a.N * I.a.N, (long long)I.a.N * I.a.N, m.nb, m.b0, 0, I.a.L,
-                      m.tile);
+    interp_body<T, W, REGEN>(I.a, I.u + (long long)m.b0 * I.a.N * I.a.N, (long long)I.a.N * I.a.N, m.nb, m.b0, 0,
+                             I.a.L, m.tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -650,14 +689,28 @@ PlanArgs<T> make_args(const fio_plan_s *P) {
     a.G = static_cast<cplx<T> *>(P->d_G);
     a.H_stride = P->H_total;
     a.G_stride = P->G_total;
+    a.zcol = static_cast<const double2 *>(P->d_zcol);
+    a.zmat = static_cast<const double2 *>(P->d_zmat);
     return a;
+}
+
+// Dynamic LDS of the interpolation: the window, plus the regenerated
+// gamma^x of the tile's points (kThreads x qmax complex) in FIO_FACTORS_REGEN.
+template <typename T>
+size_t interp_lds_bytes(bool regen, int qmax) {
+    return kInterpLdsBytes + (regen ? (size_t)kThreads * qmax * sizeof(cplx<T>) : 0);
 }
 
 template <typename T, int W>
 static hipError_t launch_interp_w(const fio_plan_s *P, const PlanArgs<T> &a, cplx<T> *u, long long ustride, int B,
                                   int bofs, int l0, int l1, hipStream_t s) {
     const int tiles = (P->N + kTileX - 1) / kTileX;
-    k_interp<T, W><<<(unsigned)(tiles * tiles), kThreads, kInterpLdsBytes, s>>>(a, u, ustride, B, bofs, l0, l1);
+    if (P->regen)
+        k_interp<T, W, true><<<(unsigned)(tiles * tiles), kThreads, interp_lds_bytes<T>(true, P->qmax), s>>>(
+            a, u, ustride, B, bofs, l0, l1);
+    else
+        k_interp<T, W, false><<<(unsigned)(tiles * tiles), kThreads, kInterpLdsBytes, s>>>(a, u, ustride, B, bofs,
+                                                                                            l0, l1);
     return hipGetLastError();
 }
 
@@ -736,14 +789,32 @@ static hipError_t apply_t(fio_plan_s *P, int B, const void *fhat, void *u, hipSt
     return hipSuccess;
 }
 
+template <typename T, int... Ws>
+static hipError_t set_interp_lds_limits() {
+    hipError_t e = hipSuccess;
+    // the regenerating variants take the window plus kThreads x kRegenMaxRank complex
+    ((e = e != hipSuccess ? e
+                          : hipFuncSetAttribute(reinterpret_cast<const void *>(&k_interp<T, Ws, true>),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes)),
+     ...);
+    ((e = e != hipSuccess ? e
+                          : hipFuncSetAttribute(reinterpret_cast<const void *>(&k_interp_multi<T, Ws, true>),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes)),
+     ...);
+    return e;
+}
+
 template <typename T>
 static hipError_t set_lds_limits() {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_rows<T>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
     if (e != hipSuccess)
         return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cols<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               kMaxLdsBytes);
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cols<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kMaxLdsBytes);
+    if (e != hipSuccess)
+        return e;
+    return set_interp_lds_limits<T, 4, 5, 6, 7, 8, 10, 12, 14, 16>();
 }
 
 __global__ void k_zero(unsigned long long *__restrict__ p, long long n) {
@@ -766,8 +837,12 @@ static void launch_multi_w(const MultiLaunch &ml, hipStream_t s) {
         k_rows_multi<T><<<ml.nrows, kFftThreads, ml.lds_rows, s>>>(I, ml.rows);
     if (ml.ncols)
         k_cols_multi<T><<<ml.ncols, kColThreads, ml.lds_cols, s>>>(I, ml.cols);
-    if (ml.ntiles)
-        k_interp_multi<T, W><<<ml.ntiles, kThreads, kInterpLdsBytes, s>>>(I, ml.tiles);
+    if (ml.ntiles) {
+        if (ml.regen)
+            k_interp_multi<T, W, true><<<ml.ntiles, kThreads, ml.lds_interp, s>>>(I, ml.tiles);
+        else
+            k_interp_multi<T, W, false><<<ml.ntiles, kThreads, kInterpLdsBytes, s>>>(I, ml.tiles);
+    }
 }
 
 template <typename T>

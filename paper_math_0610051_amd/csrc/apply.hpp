@@ -10,6 +10,7 @@ namespace fio {
 constexpr int kThreads = 256;       // workgroup size of every apply kernel
 constexpr int kInterpBatch = 8;     // right-hand sides per interpolation launch
 constexpr int kTileX = 16;          // interpolation tile: kTileX x kTileX output points per workgroup
+constexpr int kRegenMaxRank = 16;      // padded rank bound of FIO_FACTORS_REGEN (FP32; half in FP64)
 constexpr int kInterpLdsBytes = 49152;  // LDS windows (rank planes of several right-hand sides) per interpolation workgroup
 constexpr int kMaxLdsBytes = 131072;  // largest dynamic LDS request of any apply kernel
 constexpr int kFftThreads = 512;     // workgroup size of the two FFT stages
@@ -47,6 +48,8 @@ struct MultiLaunch {
     const MultiTile *tiles = nullptr;
     unsigned nrows = 0, ncols = 0, ntiles = 0;
     size_t lds_rows = 0, lds_cols = 0;
+    bool regen = false;          // FIO_FACTORS_REGEN plans (all instances alike)
+    size_t lds_interp = 0;       // dynamic LDS of the interpolation launch
 };
 hipError_t multi_launch(const MultiLaunch &ml, hipStream_t s);
 size_t inst_args_size(int precision);

@@ -90,6 +90,13 @@ static fio_status build_state(MultiState &st, int n, const fio_plan_t *plans, co
     st.ml.ntiles = (unsigned)tiles.size();
     st.ml.lds_rows = lds_rows;
     st.ml.lds_cols = lds_cols;
+    st.ml.regen = plans[0]->regen;
+    {
+        int qmax = 0;
+        for (int i = 0; i < n; ++i)
+            qmax = std::max(qmax, plans[i]->qmax);
+        st.ml.lds_interp = kInterpLdsBytes + (st.ml.regen ? (size_t)kThreads * qmax * plans[0]->esize : 0);
+    }
     // capture the three launches once
     FIO_HIP_TRY(hipStreamCreateWithFlags(&st.cap, hipStreamNonBlocking));
     FIO_HIP_TRY(hipStreamBeginCapture(st.cap, hipStreamCaptureModeThreadLocal));
@@ -112,7 +119,7 @@ fio_status multi_apply(int n, const fio_plan_t *plans, const void *const *fhat, 
                        hipStream_t s) {
     bool fused = true;
     for (int i = 0; i < n; ++i)
-        if (plans[i]->w != plans[0]->w || B[i] > plans[i]->bchunk)
+        if (plans[i]->w != plans[0]->w || plans[i]->regen != plans[0]->regen || B[i] > plans[i]->bchunk)
             fused = false;
     if (!fused)
         return run_sequential(n, plans, fhat, u, B, s);

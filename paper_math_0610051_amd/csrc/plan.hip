@@ -645,7 +645,20 @@ static fio_status store_factors(fio_plan_s *P, const double2 *d_xcoef, bool exac
             continue;
         const double e1 = std::cos(W.theta), e2 = std::sin(W.theta);
         const int rc = (int)W.C.size(), rr = (int)W.R.size();
-        if (exact_x) {
+        if (exact_x && P->regen) {
+            // the compressed factors: column frequencies and Z zero-padded to qpad ranks
+            std::vector<double2> cols(rc), zp((size_t)rc * W.qpad, make_double2(0, 0));
+            for (int c = 0; c < rc; ++c) {
+                const int om = W.members[W.C[c]];
+                cols[c] = make_double2(om / N - h, om % N - h);
+                for (int t = 0; t < W.q; ++t)
+                    zp[(size_t)c * W.qpad + t] = make_double2(W.Z[(size_t)c * W.q + t].real(), W.Z[(size_t)c * W.q + t].imag());
+            }
+            FIO_HIP_TRY(hipMemcpy(static_cast<double2 *>(P->d_zcol) + D.zc_off, cols.data(), rc * sizeof(double2),
+                                  hipMemcpyHostToDevice));
+            FIO_HIP_TRY(hipMemcpy(static_cast<double2 *>(P->d_zmat) + D.zm_off, zp.data(), zp.size() * sizeof(double2),
+                                  hipMemcpyHostToDevice));
+        } else if (exact_x) {
             std::vector<double2> cols(rc);
             for (int c = 0; c < rc; ++c) {
                 const int om = W.members[W.C[c]];
@@ -743,7 +756,8 @@ static fio_status plan_geometry(fio_plan_s *P) {
 void release_layout(fio_plan_s *P) {
     void **bufs[] = {(void **)&P->d_wedges, (void **)&P->d_fftplans, (void **)&P->d_rows, (void **)&P->d_cols,
                      (void **)&P->d_map,    (void **)&P->d_omega,    &P->d_gxi,             &P->d_gx,
-                     &P->d_tw,              &P->d_H,                 &P->d_G};
+                     &P->d_tw,              &P->d_H,                 &P->d_G,               &P->d_zcol,
+                     &P->d_zmat};
     for (void **b : bufs) {
         if (*b)
             (void)hipFree(*b);
@@ -767,7 +781,7 @@ static fio_status plan_layout(fio_plan_s *P) {
     P->wdev.assign(P->L, WedgeDev());
     P->rows.clear();
     P->cols.clear();
-    long long map_off = 0, mem_off = 0, gxi_off = 0, gx_off = 0, H_off = 0, G_off = 0;
+    long long map_off = 0, mem_off = 0, gxi_off = 0, gx_off = 0, H_off = 0, G_off = 0, zc_off = 0, zm_off = 0;
     P->row_first.assign(P->L + 1, 0);
     P->col_first.assign(P->L + 1, 0);
     size_t lds_rows = 0, lds_cols = 0;
@@ -816,7 +830,16 @@ static fio_status plan_layout(fio_plan_s *P) {
         D.gxi_off = gxi_off;
         gxi_off += (long long)W.members.size() * W.qpad;
         D.gx_off = gx_off;
-        gx_off += NN * W.qpad;
+        D.zc_off = zc_off;
+        D.zm_off = zm_off;
+        D.zrc = 0;
+        if (P->regen) {
+            D.zrc = (int)W.C.size();
+            zc_off += W.C.size();
+            zm_off += (long long)W.C.size() * W.qpad;
+        } else {
+            gx_off += NN * W.qpad;
+        }
         D.H_off = H_off;
         H_off += (long long)W.B[0] * W.n[1] * W.qpad;
         D.G_off = G_off;
@@ -909,6 +932,11 @@ static fio_status plan_layout(fio_plan_s *P) {
     FIO_HIP_TRY(hipMalloc(&P->d_gxi, es * std::max<long long>(1, gxi_off)));
     FIO_HIP_TRY(hipMalloc(&P->d_gx, es * std::max<long long>(1, gx_off)));
     P->factor_bytes = (long long)es * (gxi_off + gx_off);
+    if (P->regen) {
+        FIO_HIP_TRY(hipMalloc(&P->d_zcol, sizeof(double2) * std::max<long long>(1, zc_off)));
+        FIO_HIP_TRY(hipMalloc(&P->d_zmat, sizeof(double2) * std::max<long long>(1, zm_off)));
+        P->factor_bytes += (long long)sizeof(double2) * (zc_off + zm_off);
+    }
     // workspace: bchunk right-hand sides
     P->bchunk = std::max(1, P->opt.max_batch);
     const long long per_rhs = (long long)es * (H_off + G_off);
@@ -939,10 +967,21 @@ static fio_status plan_exact(fio_plan_s *P, const double2 *d_xcoef) {
                         FIO_EACCURACY);
         }
     }
+    P->regen = P->opt.factor_mode == FIO_FACTORS_REGEN;
+    if (P->regen) {
+        int qmax = 0;
+        for (const WedgeHost &W : P->wedges)
+            qmax = std::max(qmax, W.q + (W.q & 1));
+        if (qmax > kRegenMaxRank / (P->precision == FIO_F64 ? 2 : 1))
+            return (set_error("FIO_FACTORS_REGEN needs a padded rank of at most " +
+                              std::to_string(kRegenMaxRank / (P->precision == FIO_F64 ? 2 : 1)) + " (have " +
+                              std::to_string(qmax) + ")"),
+                    FIO_ENOTSUP);
+    }
     fio_status st = plan_layout(P);
     if (st != FIO_OK)
         return st;
-    P->factor_mode = FIO_FACTORS_STORED;
+    P->factor_mode = P->regen ? FIO_FACTORS_REGEN : FIO_FACTORS_STORED;
     return P->precision == FIO_F64 ? store_factors<double>(P, d_xcoef, true) : store_factors<float>(P, d_xcoef, true);
 }
 
@@ -1058,7 +1097,8 @@ fio_status build_plan(fio_plan_s *P) {
     k_xcoef<<<(unsigned)((NN + 255) / 256), 256>>>(P->phase, N, d_xcoef);
     FIO_HIP_TRY(hipGetLastError());
     LearnedModel *net = static_cast<LearnedModel *>(const_cast<void *>(P->opt.learned));
-    const bool want_net = net && P->opt.factor_mode != FIO_FACTORS_STORED;
+    const bool want_net =
+        net && (P->opt.factor_mode == FIO_FACTORS_AUTO || P->opt.factor_mode == FIO_FACTORS_LEARNED);
     bool use_net = want_net;
     if (want_net && (net->N != N || net->L != P->L || P->opt.partition != FIO_PART_EQUIANGULAR ||
                      P->precision != FIO_F32 || net->family.kind != P->phase.kind)) {

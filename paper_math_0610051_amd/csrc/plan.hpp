@@ -34,6 +34,9 @@ struct WedgeDev {
     long long H_off;     // per-RHS row-transformed box, [j2][k1][rank]: n2 * B1 * q complex
     long long G_off;     // per-RHS oversampled grid, [j2][j1][rank]: n2 * n1 * q complex
     FastDiv fq, fB1, fB2, fn1, fn2;  // dividers by q, B1, B2, n1, n2 (constants built on the host)
+    long long zc_off;    // regenerated factors: sampled column frequencies (zrc of them)
+    long long zm_off;    // and Z = V S^-1, zrc * q complex double (zero-padded ranks)
+    int zrc, pad2;       // number of sampled columns (0 when gamma^x is stored)
 };
 
 // Work items of the two FFT stages.
@@ -66,6 +69,8 @@ struct PlanArgs {
     cplx<T> *H;
     cplx<T> *G;
     long long H_stride, G_stride;  // per right-hand side
+    const double2 *zcol;           // regenerated factors (FIO_FACTORS_REGEN)
+    const double2 *zmat;
 };
 
 struct WedgeHost {
@@ -97,6 +102,8 @@ struct fio_plan_s {
     int fallback = 0, factor_mode = FIO_FACTORS_STORED;
     double plan_ms = 0;
     double learned_sep_err = 0, learned_ms = 0;  // the learned attempt, if any
+    bool regen = false;                          // gamma^x recomputed in the apply
+    void *d_zcol = nullptr, *d_zmat = nullptr;
     std::vector<fio::WedgeHost> wedges;
     std::vector<int> wedge_of;   // N*N, centred
     std::vector<fio::WedgeDev> wdev;

@@ -301,6 +301,40 @@ def test_other_oversampling_factors_full_grid(sigma):
     assert err <= tol
 
 
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_regenerated_factors_match_stored_ones(precision):
+    """FIO_FACTORS_REGEN keeps only the compressed factors (sampled columns and
+    Z = V S^-1) and recomputes gamma^x in the apply.  With the same seed the
+    separation is the same, so the apply must agree with the stored-factor
+    plan to rounding, meet the tolerance, and hold far fewer factor bytes."""
+    N, tol = 128, 1e-4
+    rng = fi.rng_for(1, 5)
+    fh = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=3))
+    ps = _plan(N, "c1c2", (1.0,), tol, precision=precision, factor_mode="stored", seed=77)
+    pr = _plan(N, "c1c2", (1.0,), tol, precision=precision, factor_mode="regen", seed=77)
+    assert pr.info()["factor_mode"] == 2
+    us = _apply(ps, fh, precision).reshape(3, N * N)
+    ur = _apply(pr, fh, precision).reshape(3, N * N)
+    diff = ref.rel_l2(ur, us)
+    exact = od.direct(N, 2, (1.0,), fh, np.arange(N * N))
+    err = ref.rel_l2(ur, exact)
+    fs, fr = ps.info()["factor_bytes"], pr.info()["factor_bytes"]
+    print("  %s: regen vs stored %.2e, regen vs direct %.2e, factor bytes %d -> %d"
+          % (precision, diff, err, fs, fr))
+    assert diff < (2e-6 if precision == "f32" else 1e-12)
+    assert err <= tol
+    assert fr * 4 < fs
+    # the exported spatial factors agree: host FP64 regeneration against the
+    # stored ones (device FP64, then the plan precision); host and device
+    # exponentials differ in the last bits, which the sum with Z ~ 1/s_q
+    # amplifies, hence 1e-10 in FP64
+    xs = np.arange(0, N * N, 97)
+    for ell in (0, pr.L // 3):
+        gr, _ = pr.wedge_factors(ell, xs)
+        gs, _ = ps.wedge_factors(ell, xs)
+        assert np.linalg.norm(gr - gs) <= (1e-6 if precision == "f32" else 1e-10) * np.linalg.norm(gs)
+
+
 def test_fp64_long_columns_in_rank_chunks():
     """FP64 at a tight tolerance: when a grid column of all ranks exceeds the
     LDS transform buffer (n1 * qpad > 4096 complex doubles), the column stage
