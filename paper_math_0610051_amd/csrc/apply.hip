@@ -24,8 +24,9 @@ namespace fio {
 // Stage 1: window x factor -> box rows, FFT along axis 2 (length n2, the short
 // side of the box).  One workgroup per (wedge, nr adjacent box rows, rank
 // chunk); loops over the batch; in-place LDS transform of nr * tn sequences.
-// H is stored column-major in cells, [j2][k1][rank], so the nr rows of one
-// column j2 leave as one contiguous run.
+// H is plane-major: plane P = j2 * qu + t / CPU (CPU complex per 16 bytes)
+// holds element [(P * B1 + k1) * CPU + t % CPU], so the nr rows of one
+// (column, plane) leave as one contiguous run.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it, const cplx<T> *__restrict__ fhat,
@@ -107,11 +108,25 @@ __device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it
         }
         __syncthreads();
         fft_inplace<T, E>(buf, pl, n, nbt, fnbt, twl, tid, nt);
-        // buf[j2 * nbt + r * tn + t] -> H[(j2 * B1 + k1 + r) * q + t0 + t]
-        cplx<T> *H = a.H + b * a.H_stride + W.H_off + (long long)it.k1 * q + it.t0;
-        for (int i = tid; i < n * nbt; i += nt) {
-            const int j2 = fnbt.div(i), c = i - j2 * nbt, r = ftn.div(c), t = c - r * tn;
-            H[((long long)j2 * B1 + r) * q + t] = buf[i];
+        // buf[j2 * nbt + r * tn + t] -> H[((j2 * qu + (t0 + t) / CPU) * B1 + k1 + r) * CPU + (t0 + t) % CPU]
+        constexpr int CPU = 16 / (int)sizeof(cplx<T>);
+        const int qu = q / CPU;
+        cplx<T> *H = a.H + b * a.H_stride + W.H_off;
+        if (tn % CPU == 0 && it.t0 % CPU == 0) {
+            // whole planes: flat i = ((j2 * npl + pl) * nr + r) * CPU + c follows H
+            const int npl = tn / CPU;
+            for (int i = tid; i < n * nbt; i += nt) {
+                const int c = i % CPU, g = i / CPU;  // g = (j2 * npl + pl) * nr + r
+                const int jp = it.fnr.div(g), r = g - jp * nr;
+                const int j2 = it.fnpl.div(jp), pl = jp - j2 * npl;
+                H[((long long)(j2 * qu + it.t0 / CPU + pl) * B1 + it.k1 + r) * CPU + c] =
+                    buf[j2 * nbt + r * tn + pl * CPU + c];
+            }
+        } else {
+            for (int i = tid; i < n * nbt; i += nt) {
+                const int j2 = fnbt.div(i), cc = i - j2 * nbt, r = ftn.div(cc), t = it.t0 + cc - r * tn;
+                H[((long long)(j2 * qu + t / CPU) * B1 + it.k1 + r) * CPU + t % CPU] = buf[i];
+            }
         }
         __syncthreads();
     }
@@ -158,42 +173,41 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
     const FastDiv &fnb = it.fnb, &fq = W.fq, &fb1 = W.fB1, &fn = W.fn1;
     const cplx<T> *H = a.H + (long long)b * a.H_stride + W.H_off;
     cplx<T> *G = a.G + (long long)b * a.G_stride + W.G_off;
-    const bool whole = nb >= q;  // whole columns: tau0 = j2_0 * q, nb = ncol * q
-    const int j20 = fq.div(it.tau0), t0 = it.tau0 - j20 * q;
+    // H is plane-major (plane P = tau / CPU, element [(P * B1 + k1) * CPU + tau % CPU]): an item of
+    // whole planes reads one contiguous block.  G is cell-major [j2][j1][rank], which keeps the
+    // window columns that the interpolation stages contiguous over all ranks.
+    constexpr int CPU = 16 / (int)sizeof(cplx<T>);
+    const bool whole = nb % CPU == 0 && it.tau0 % CPU == 0;
     if (whole) {
-        // flat i = (col * B1 + k1) * q + t over the columns' contiguous runs
+        // flat i = (p * B1 + k1) * CPU + c
         const cplx<T> *src = H + (long long)it.tau0 * B1;
         for (int i = tid; i < B1 * nb; i += nt) {
-            const int kq = fq.div(i), t = i - kq * q;  // kq = col * B1 + k1
-            const int col = fb1.div(kq), k1 = kq - col * B1;
+            const int c = i % CPU, g = i / CPU;
+            const int p = fb1.div(g), k1 = g - p * B1;
             int j1 = lo1 + k1;
             if (j1 < 0)
                 j1 += n;
-            buf[j1 * nb + col * q + t] = src[i];
+            buf[j1 * nb + p * CPU + c] = src[i];
         }
     } else {
+        // single ranks of one plane
+        const int P = it.tau0 / CPU, c0 = it.tau0 % CPU;
         for (int i = tid; i < B1 * nb; i += nt) {
             const int k1 = fnb.div(i), c = i - k1 * nb;
             int j1 = lo1 + k1;
             if (j1 < 0)
                 j1 += n;
-            buf[j1 * nb + c] = H[((long long)j20 * B1 + k1) * q + t0 + c];
+            buf[j1 * nb + c] = H[((long long)P * B1 + k1) * CPU + c0 + c];
         }
     }
     __syncthreads();
     fft_inplace<T, E>(buf, pl, n, nb, fnb, twl, tid, nt);
-    if (whole) {
-        cplx<T> *dstp = G + (long long)it.tau0 * n;
-        for (int i = tid; i < n * nb; i += nt) {
-            const int jq = fq.div(i), t = i - jq * q;  // jq = col * n + j1
-            const int col = fn.div(jq), j1 = jq - col * n;
-            dstp[i] = buf[j1 * nb + col * q + t];
-        }
-    } else {
-        for (int i = tid; i < n * nb; i += nt) {
-            const int j1 = fnb.div(i), c = i - j1 * nb;
-            G[((long long)j20 * n + j1) * q + t0 + c] = buf[i];
-        }
+    // tau = j2 * q + t -> G[(j2 * n + j1) * q + t]; flat i = j1 * nb + c runs over the item's ranks
+    // of a cell before the next cell
+    for (int i = tid; i < n * nb; i += nt) {
+        const int j1 = fnb.div(i), c = i - j1 * nb;
+        const int tau = it.tau0 + c, j2 = fq.div(tau), t = tau - j2 * q;
+        G[((long long)j2 * n + j1) * q + t] = buf[i];
     }
 }
 
@@ -479,8 +493,8 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         const cplx<T> mod = cmake(cs, sn);
         const cplx<T> *G0 = a.G + (long long)bofs * a.G_stride + wd.G_off;
         if (staged) {
-            // source offsets (complex, rank 0) and window positions of this
-            // thread's cells, in column-major cell order (G is [j2][j1][rank])
+            // source offsets (rank 0) and window positions of this thread's
+            // cells, in column-major cell order (G is [j2][j1][rank])
             // J1 > -W and J1 + F1 <= 2 m1 (likewise for axis 2), so one
             // conditional wrap brings every window cell onto the grid
             int off[kOff], dst[kOff];
@@ -649,15 +663,18 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
 // the default budget, which it needs to avoid spills.
 template <typename T>
 constexpr int kInterpWavesPerEU = sizeof(T) == 4 ? 3 : 1;
+// the 48 KB window allows three workgroups per CU, so more waves would not fit
+template <typename T>
+constexpr int kInterpWavesPerEUMax = sizeof(T) == 4 ? 3 : 2;
 
 template <typename T, int W, bool REGEN>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T>))) void k_interp(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T>, kInterpWavesPerEUMax<T>))) void k_interp(
     PlanArgs<T> a, cplx<T> *__restrict__ u, long long ustride, int B, int bofs, int l0, int l1) {
     interp_body<T, W, REGEN>(a, u, ustride, B, bofs, l0, l1, blockIdx.x);
 }
 
 template <typename T, int W, bool REGEN>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T>))) void k_interp_multi(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T>, kInterpWavesPerEUMax<T>))) void k_interp_multi(
     const InstArgs<T> *__restrict__ inst, const MultiTile *__restrict__ tiles) {
     const MultiTile m = tiles[blockIdx.x];
     const InstArgs<T> &I = inst[m.inst];

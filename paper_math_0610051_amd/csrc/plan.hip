@@ -844,30 +844,35 @@ static fio_status plan_layout(fio_plan_s *P) {
         H_off += (long long)W.B[0] * W.n[1] * W.qpad;
         D.G_off = G_off;
         G_off += (long long)W.n[0] * W.n[1] * W.qpad;
-        // stage-1 items: nr adjacent box rows with all ranks when they fit the
-        // LDS buffer, else single rows in rank chunks
-        const int tn = (int)std::max<long long>(1, std::min<long long>(W.qpad, cap / W.n[1]));
-        const int nr = tn == W.qpad ? (int)std::max<long long>(1, std::min<long long>(W.B[0], cap / ((long long)W.n[1] * tn))) : 1;
+        // H is plane-major: plane P = j2 * qu + t / cpu holds ranks
+        // [cpu (t / cpu), cpu (t / cpu + 1)) of grid column j2, element
+        // [(P * B1 + k1) * cpu + t % cpu] (cpu = complex per 16 bytes); G is
+        // cell-major, [(j2 * n1 + j1) * q + t].
+        const int cpu = (int)(16 / P->esize), qu = W.qpad / cpu;
+        // stage-1 items: nr adjacent box rows and tn ranks (whole planes),
+        // aiming at 8 or more rows so each (column, plane) leaves as a run of
+        // at least 128 bytes
+        int tn = cpu * (int)std::max<long long>(1, std::min<long long>(qu, cap / ((long long)W.n[1] * 8 * cpu)));
+        if ((long long)W.n[1] * tn > cap)
+            tn = (int)std::max<long long>(1, cap / W.n[1]);  // sub-plane chunks (very long rows)
+        const int nr = (int)std::max<long long>(1, std::min<long long>(W.B[0], cap / ((long long)W.n[1] * tn)));
         for (int k1 = 0; k1 < W.B[0]; k1 += nr)
             for (int t0 = 0; t0 < W.qpad; t0 += tn)
-                P->rows.push_back(make_row_item(l, k1, std::min(nr, W.B[0] - k1), t0, std::min(tn, W.qpad - t0)));
+                P->rows.push_back(make_row_item(l, k1, std::min(nr, W.B[0] - k1), t0, std::min(tn, W.qpad - t0), cpu));
         lds_rows = std::max(lds_rows, (size_t)W.n[1] * (nr * tn + 1) * P->esize);  // buffer + twiddles
-        // stage-2 items: whole cell columns (all ranks of ncol adjacent j2) when
-        // one column fits, else rank ranges of one column (a divisor of q)
-        const long long colsz = (long long)W.n[0] * W.qpad;
-        if (colsz <= capc) {
-            const int ncol = (int)std::min<long long>(W.n[1], capc / colsz);
-            for (int j2 = 0; j2 < W.n[1]; j2 += ncol)
-                P->cols.push_back(make_col_item(l, j2 * W.qpad, std::min(ncol, W.n[1] - j2) * W.qpad));
-            lds_cols = std::max(lds_cols, (size_t)(colsz * ncol + W.n[0]) * P->esize);  // buffer + twiddles
+        // stage-2 items: whole planes (one contiguous block of H per item), or
+        // single ranks when one plane does not fit the buffer
+        const long long plsz = (long long)W.n[0] * cpu;
+        if (plsz <= capc) {
+            const long long npl = (long long)W.n[1] * qu;
+            const int np = (int)std::min<long long>(npl, capc / plsz);
+            for (long long p0 = 0; p0 < npl; p0 += np)
+                P->cols.push_back(make_col_item(l, (int)(p0 * cpu), (int)(std::min<long long>(np, npl - p0) * cpu)));
+            lds_cols = std::max(lds_cols, (size_t)(plsz * np + W.n[0]) * P->esize);  // buffer + twiddles
         } else {
-            int nb = W.qpad;
-            while (nb > 1 && ((long long)nb * W.n[0] > capc || W.qpad % nb))
-                --nb;
-            for (int j2 = 0; j2 < W.n[1]; ++j2)
-                for (int t0 = 0; t0 < W.qpad; t0 += nb)
-                    P->cols.push_back(make_col_item(l, j2 * W.qpad + t0, nb));
-            lds_cols = std::max(lds_cols, (size_t)W.n[0] * (nb + 1) * P->esize);  // buffer + twiddles
+            for (long long t0 = 0; t0 < (long long)W.n[1] * W.qpad; ++t0)
+                P->cols.push_back(make_col_item(l, (int)t0, 1));
+            lds_cols = std::max(lds_cols, (size_t)W.n[0] * 2 * P->esize);  // buffer + twiddles
         }
     }
     P->row_first[P->L] = (int)P->rows.size();

@@ -2,6 +2,7 @@
 // descriptors the kernels read).
 #pragma once
 
+#include <algorithm>
 #include <complex>
 #include <string>
 #include <vector>
@@ -31,8 +32,8 @@ struct WedgeDev {
     long long mem_off;   // member tables: centred Omega index per member
     long long gxi_off;   // gamma^xi (deconvolved, 1/N folded in), nmem * q complex
     long long gx_off;    // gamma^x, N^2 * q complex
-    long long H_off;     // per-RHS row-transformed box, [j2][k1][rank]: n2 * B1 * q complex
-    long long G_off;     // per-RHS oversampled grid, [j2][j1][rank]: n2 * n1 * q complex
+    long long H_off;     // per-RHS row-transformed box, plane-major [j2][plane][k1][rank in plane]: n2 * B1 * q complex
+    long long G_off;     // per-RHS oversampled grid, cell-major [j2][j1][rank]: n2 * n1 * q complex
     FastDiv fq, fB1, fB2, fn1, fn2;  // dividers by q, B1, B2, n1, n2 (constants built on the host)
     long long zc_off;    // regenerated factors: sampled column frequencies (zrc of them)
     long long zm_off;    // and Z = V S^-1, zrc * q complex double (zero-padded ranks)
@@ -42,14 +43,15 @@ struct WedgeDev {
 // Work items of the two FFT stages.
 struct RowItem {   // stage 1: box rows [k1, k1 + nr) of wedge ell, ranks [t0, t0 + tn)
     int l, k1, nr, t0, tn, pad;
-    FastDiv ftn, fnbt;  // dividers by tn and nr * tn
+    FastDiv ftn, fnbt, fnr, fnpl;  // dividers by tn, nr * tn, nr and the planes tn / cpu
 };
-struct ColItem {   // stage 2: transforms tau in [tau0, tau0 + nb) of wedge ell (tau = j2 * q + t)
+struct ColItem {   // stage 2: transforms tau in [tau0, tau0 + nb) of wedge ell (tau = j2 * q + t, plane tau / cpu)
     int l, tau0, nb, pad;
     FastDiv fnb;        // divider by nb
 };
-inline RowItem make_row_item(int l, int k1, int nr, int t0, int tn) {
-    return RowItem{l, k1, nr, t0, tn, 0, FastDiv((unsigned)tn), FastDiv((unsigned)(nr * tn))};
+inline RowItem make_row_item(int l, int k1, int nr, int t0, int tn, int cpu) {
+    return RowItem{l,  k1, nr, t0, tn, 0, FastDiv((unsigned)tn), FastDiv((unsigned)(nr * tn)), FastDiv((unsigned)nr),
+                   FastDiv((unsigned)std::max(1, tn / cpu))};
 }
 inline ColItem make_col_item(int l, int tau0, int nb) { return ColItem{l, tau0, nb, 0, FastDiv((unsigned)nb)}; }
 
