@@ -661,20 +661,25 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
 // FP32: at most 168 VGPRs, so that three workgroups share a SIMD (the
 // compiler otherwise hoists whole stencil planes into registers); FP64 keeps
 // the default budget, which it needs to avoid spills.
-template <typename T>
-constexpr int kInterpWavesPerEU = sizeof(T) == 4 ? 3 : 1;
-// the 48 KB window allows three workgroups per CU, so more waves would not fit
-template <typename T>
-constexpr int kInterpWavesPerEUMax = sizeof(T) == 4 ? 3 : 2;
+// Occupancy targets of the FP32 interpolation: four waves per SIMD (128
+// VGPRs, matching the four workgroups per CU that the 38 KB window allows)
+// for widths up to 5, three for width 6 and two for wider stencils, whose
+// planes need more registers, and one fewer when gamma^x is regenerated;
+// FP64 keeps the compiler's choice.
+template <typename T, int W, bool REGEN>
+constexpr int kInterpWavesPerEU =
+    sizeof(T) == 4 ? (W <= 5 ? 4 : (W == 6 ? 3 : 2)) - (REGEN ? 1 : 0) : 1;
+template <typename T, int W, bool REGEN>
+constexpr int kInterpWavesPerEUMax = sizeof(T) == 4 ? kInterpWavesPerEU<T, W, REGEN> : 2;
 
 template <typename T, int W, bool REGEN>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T>, kInterpWavesPerEUMax<T>))) void k_interp(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T, W, REGEN>, kInterpWavesPerEUMax<T, W, REGEN>))) void k_interp(
     PlanArgs<T> a, cplx<T> *__restrict__ u, long long ustride, int B, int bofs, int l0, int l1) {
     interp_body<T, W, REGEN>(a, u, ustride, B, bofs, l0, l1, blockIdx.x);
 }
 
 template <typename T, int W, bool REGEN>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T>, kInterpWavesPerEUMax<T>))) void k_interp_multi(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T, W, REGEN>, kInterpWavesPerEUMax<T, W, REGEN>))) void k_interp_multi(
     const InstArgs<T> *__restrict__ inst, const MultiTile *__restrict__ tiles) {
     const MultiTile m = tiles[blockIdx.x];
     const InstArgs<T> &I = inst[m.inst];

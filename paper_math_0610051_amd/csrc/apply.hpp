@@ -11,7 +11,7 @@ constexpr int kThreads = 256;       // workgroup size of every apply kernel
 constexpr int kInterpBatch = 8;     // right-hand sides per interpolation launch
 constexpr int kTileX = 16;          // interpolation tile: kTileX x kTileX output points per workgroup
 constexpr int kRegenMaxRank = 16;      // padded rank bound of FIO_FACTORS_REGEN (FP32; half in FP64)
-constexpr int kInterpLdsBytes = 49152;  // LDS windows (rank planes of several right-hand sides) per interpolation workgroup
+constexpr int kInterpLdsBytes = 38912;  // LDS windows (rank planes of several right-hand sides) per interpolation workgroup: four per CU
 constexpr int kMaxLdsBytes = 131072;  // largest dynamic LDS request of any apply kernel
 constexpr int kFftThreads = 512;     // workgroup size of the two FFT stages
 constexpr int kFftWavesPerEU = 4;    // register budget: two FFT workgroups per CU overlap load, transform and store
