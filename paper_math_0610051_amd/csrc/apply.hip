@@ -21,6 +21,30 @@
 namespace fio {
 
 // ---------------------------------------------------------------------------
+// Pruned first pass.  When the nonzeros of a length-n sequence fill at most
+// half of it around index 0 (a centred box in an oversampled grid), every pair
+// (x[j], x[j + n/2]) holds at most one of them, and the plan's leading
+// radix-2 Stockham pass turns x into buf[2j] = x and buf[2j + 1] = +x for
+// j < n/2, or -x above.  slot_code packs the buffer position of input index
+// j at column col (row stride `stride`) with the sign in bit 0; store_slot
+// writes the value (and, pruned, its partner).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int slot_code(bool pruned, int j, int n, int stride, int col) {
+    if (!pruned)
+        return (j * stride + col) << 1;
+    const int h = n >> 1;
+    return j < h ? ((2 * j * stride + col) << 1) : (((2 * (j - h)) * stride + col) << 1) | 1;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_slot(cplx<T> *buf, int code, int stride, bool pruned, cplx<T> v) {
+    const int pos = code >> 1;
+    buf[pos] = v;
+    if (pruned)
+        buf[pos + stride] = (code & 1) ? cmake<T>(-v.re, -v.im) : v;
+}
+
+// ---------------------------------------------------------------------------
 // Stage 1: window x factor -> box rows, FFT along axis 2 (length n2, the short
 // side of the box).  One workgroup per (wedge, nr adjacent box rows, rank
 // chunk); loops over the batch; in-place LDS transform of nr * tn sequences.
@@ -42,6 +66,8 @@ __device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it
     for (int i = tid; i < n; i += nt)
         twl[i] = a.tw[W.tw2 + i];
     const FastDiv &ftn = it.ftn, &fb2 = W.fB2, &fnbt = it.fnbt;
+    // the box fills at most half the row: the first radix-2 pass is folded into the scatter
+    const bool pruned = pl->radix[0] == 2 && n >= 2 * B2;
     const int *map = a.map + W.map_off + (long long)it.k1 * B2;
     const int *omega = a.omega + W.mem_off;
     const cplx<T> *gxi = a.gxi + W.gxi_off + it.t0;
@@ -67,7 +93,7 @@ __device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it
                 int j2 = lo2 + k2;
                 if (j2 < 0)
                     j2 += n;
-                dst[k] = j2 * nbt + r * tn + t;
+                dst[k] = slot_code(pruned, j2, n, nbt, r * tn + t);
                 fidx[k] = omega[m];
                 g[k] = gxi[(long long)m * q + t];
             }
@@ -88,7 +114,7 @@ __device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it
 #pragma unroll
         for (int k = 0; k < KR; ++k)
             if (dst[k] >= 0)
-                buf[dst[k]] = cmul(fv[k], g[k]);
+                store_slot(buf, dst[k], nbt, pruned, cmul(fv[k], g[k]));
         if (b + 1 < B) {
 #pragma unroll
             for (int k = 0; k < KR; ++k)
@@ -103,11 +129,12 @@ __device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it
                 int j2 = lo2 + k2;
                 if (j2 < 0)
                     j2 += n;
-                buf[j2 * nbt + r * tn + t] = cmul(f[omega[m]], gxi[(long long)m * q + t]);
+                store_slot(buf, slot_code(pruned, j2, n, nbt, r * tn + t), nbt, pruned,
+                           cmul(f[omega[m]], gxi[(long long)m * q + t]));
             }
         }
         __syncthreads();
-        fft_inplace<T, E>(buf, pl, n, nbt, fnbt, twl, tid, nt);
+        fft_inplace<T, E>(buf, pl, n, nbt, fnbt, twl, tid, nt, pruned ? 1 : 0);
         // buf[j2 * nbt + r * tn + t] -> H[((j2 * qu + (t0 + t) / CPU) * B1 + k1 + r) * CPU + (t0 + t) % CPU]
         constexpr int CPU = 16 / (int)sizeof(cplx<T>);
         const int qu = q / CPU;
@@ -167,8 +194,12 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
     cplx<T> *twl = buf + n * nb;  // the n twiddles follow the transform buffer
     for (int i = tid; i < n; i += nt)
         twl[i] = a.tw[W.tw1 + i];
-    // padding rows j1 in [B1 - B1/2, n - B1/2) are zero
-    for (int i = (B1 - B1 / 2) * nb + tid; i < (n - B1 / 2) * nb; i += nt)
+    // the box fills at most half the column: the first radix-2 pass is folded
+    // into the load, and only pairs without a box row are zeroed; otherwise
+    // the padding rows j1 in [B1 - B1/2, n - B1/2) are zeroed
+    const bool pruned = pl->radix[0] == 2 && n >= 2 * B1;
+    const int z0 = pruned ? 2 * (B1 - B1 / 2) : B1 - B1 / 2, z1 = pruned ? n - 2 * (B1 / 2) : n - B1 / 2;
+    for (int i = z0 * nb + tid; i < z1 * nb; i += nt)
         buf[i] = cmake<T>(0, 0);
     const FastDiv &fnb = it.fnb, &fq = W.fq, &fb1 = W.fB1, &fn = W.fn1;
     const cplx<T> *H = a.H + (long long)b * a.H_stride + W.H_off;
@@ -187,7 +218,7 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
             int j1 = lo1 + k1;
             if (j1 < 0)
                 j1 += n;
-            buf[j1 * nb + p * CPU + c] = src[i];
+            store_slot(buf, slot_code(pruned, j1, n, nb, p * CPU + c), nb, pruned, src[i]);
         }
     } else {
         // single ranks of one plane
@@ -197,11 +228,11 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
             int j1 = lo1 + k1;
             if (j1 < 0)
                 j1 += n;
-            buf[j1 * nb + c] = H[((long long)P * B1 + k1) * CPU + c0 + c];
+            store_slot(buf, slot_code(pruned, j1, n, nb, c), nb, pruned, H[((long long)P * B1 + k1) * CPU + c0 + c]);
         }
     }
     __syncthreads();
-    fft_inplace<T, E>(buf, pl, n, nb, fnb, twl, tid, nt);
+    fft_inplace<T, E>(buf, pl, n, nb, fnb, twl, tid, nt, pruned ? 1 : 0);
     // tau = j2 * q + t -> G[(j2 * n + j1) * q + t]; flat i = j1 * nb + c runs over the item's ranks
     // of a cell before the next cell
     for (int i = tid; i < n * nb; i += nt) {

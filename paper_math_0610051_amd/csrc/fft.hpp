@@ -13,7 +13,9 @@ namespace fio {
 
 constexpr int kMaxPasses = 24;
 
-// Radix plan of a length n = 2^a 3^b 5^c: radix 8 first, then 4/2, 3, 5.
+// Radix plan of a length n = 2^a 3^b 5^c: for even n a radix-2 pass first
+// (which a half-empty input lets the caller fold into its load, see
+// fft_inplace's first_pass), then radix 8, 4/2, 3, 5.
 // ns[p] divides flat butterfly indices by Ns = radix[0] * ... * radix[p-1].
 struct FftPlan {
     int n;
@@ -29,6 +31,10 @@ inline bool fft_make_plan(int n, FftPlan &pl) {
     int m = n;
     if (n < 1)
         return false;
+    if (m % 2 == 0) {
+        pl.radix[pl.npass++] = 2;
+        m /= 2;
+    }
     while (m % 8 == 0 && pl.npass < kMaxPasses) {
         pl.radix[pl.npass++] = 8;
         m /= 8;
@@ -221,12 +227,16 @@ __device__ __forceinline__ void stockham_pass_inplace(cplx<T> *buf, int n, int n
 
 // All passes of a length-n transform of nb interleaved sequences in place;
 // E = elements per worker the buffer holds at most (n * nb <= E * nthreads).
+// first_pass = 1 starts after the plan's leading radix-2 pass, whose output
+// the caller has already written: when every pair (x[j], x[j + n/2]) holds at
+// most one nonzero x, that pass maps it to buf[2j] = x and buf[2j + 1] = +x
+// (nonzero in the lower half) or -x (upper half).
 template <typename T, int E>
 __device__ __forceinline__ void fft_inplace(cplx<T> *buf, const FftPlan *pl, int n, int nb, const FastDiv &fnb,
-                                            const cplx<T> *twl, int tid, int nthreads) {
-    int Ns = 1;
+                                            const cplx<T> *twl, int tid, int nthreads, int first_pass = 0) {
+    int Ns = first_pass ? pl->radix[0] : 1;
     const int npass = pl->npass;
-    for (int p = 0; p < npass; ++p) {
+    for (int p = first_pass; p < npass; ++p) {
         const int R = pl->radix[p];
         const FastDiv fns = pl->ns[p];
         const int tfac = pl->tfac[p];
