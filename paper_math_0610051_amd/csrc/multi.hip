@@ -6,6 +6,7 @@
 // batch sizes) stays the same; new data pointers only refresh the argument
 // table.  Instance lists the fused path cannot take (mixed kernel widths, or a
 // batch larger than a plan's workspace) run instance after instance instead.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -56,7 +57,17 @@ static fio_status build_state(MultiState &st, int n, const fio_plan_t *plans, co
     std::vector<MultiColItem> cols;
     std::vector<MultiTile> tiles;
     size_t lds_rows = 0, lds_cols = 0;
-    for (int i = 0; i < n; ++i) {
+    // heaviest instances first (wedge count x grid points x batch), so the
+    // launch does not end on a tail of long workgroups
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        const double wx = (double)plans[x]->L * plans[x]->N * plans[x]->N * B[x];
+        const double wy = (double)plans[y]->L * plans[y]->N * plans[y]->N * B[y];
+        return wx > wy;
+    });
+    for (int i : order) {
         const fio_plan_s *P = plans[i];
         for (const RowItem &r : P->rows)
             rows.push_back(MultiRowItem{i, r});
