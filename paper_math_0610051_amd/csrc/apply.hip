@@ -14,6 +14,7 @@
 // each thread owns one output point and loops over all wedges.
 #include <cfloat>
 #include <climits>
+#include <cstdint>
 #include <cstring>
 
 #include "apply.hpp"
@@ -165,11 +166,42 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kFf
     rows_body<T>(a, items[blockIdx.x], fhat, fstride, B);
 }
 
+// A fused launch reads each instance's arguments from a device table, and
+// pointers loaded from memory are generic (flat) to the compiler: the wedge
+// records would be read with flat vector loads instead of scalar ones, and
+// every buffer access would go through flat instructions.  All of these
+// pointers address global memory; passing them through an integer into the
+// global address space restores what a kernel argument gives for free.
+template <typename P>
+__device__ __forceinline__ P *as_global(P *p) {
+    return (P *)(__attribute__((address_space(1))) P *)(uintptr_t)p;
+}
+
+template <typename T>
+__device__ __forceinline__ InstArgs<T> load_inst(const InstArgs<T> *inst, int i) {
+    InstArgs<T> I = inst[i];
+    PlanArgs<T> &a = I.a;
+    a.wedges = as_global(a.wedges);
+    a.fftplans = as_global(a.fftplans);
+    a.map = as_global(a.map);
+    a.omega = as_global(a.omega);
+    a.gxi = as_global(a.gxi);
+    a.gx = as_global(a.gx);
+    a.tw = as_global(a.tw);
+    a.H = as_global(a.H);
+    a.G = as_global(a.G);
+    a.zcol = as_global(a.zcol);
+    a.zmat = as_global(a.zmat);
+    I.fhat = as_global(I.fhat);
+    I.u = as_global(I.u);
+    return I;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kFftWavesPerEU))) void k_rows_multi(const InstArgs<T> *__restrict__ inst,
                                                             const MultiRowItem *__restrict__ items) {
-    const MultiRowItem m = items[blockIdx.x];
-    const InstArgs<T> &I = inst[m.inst];
+    const MultiRowItem &m = items[blockIdx.x];
+    const InstArgs<T> I = load_inst(inst, m.inst);
     rows_body<T>(I.a, m.it, I.fhat, (long long)I.a.N * I.a.N, I.B);
 }
 
@@ -251,8 +283,9 @@ __global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(kFf
 template <typename T>
 __global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(kFftWavesPerEU))) void k_cols_multi(
     const InstArgs<T> *__restrict__ inst, const MultiColItem *__restrict__ items) {
-    const MultiColItem m = items[blockIdx.x];
-    cols_body<T>(inst[m.inst].a, m.it, m.b);
+    const MultiColItem &m = items[blockIdx.x];
+    const InstArgs<T> I = load_inst(inst, m.inst);
+    cols_body<T>(I.a, m.it, m.b);
 }
 
 template <typename T>
@@ -713,7 +746,7 @@ template <typename T, int W, bool REGEN>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T, W, REGEN>, kInterpWavesPerEUMax<T, W, REGEN>))) void k_interp_multi(
     const InstArgs<T> *__restrict__ inst, const MultiTile *__restrict__ tiles) {
     const MultiTile m = tiles[blockIdx.x];
-    const InstArgs<T> &I = inst[m.inst];
+    const InstArgs<T> I = load_inst(inst, m.inst);
     interp_body<T, W, REGEN>(I.a, I.u + (long long)m.b0 * I.a.N * I.a.N, (long long)I.a.N * I.a.N, m.nb, m.b0, 0,
                              I.a.L, m.tile);
 }
