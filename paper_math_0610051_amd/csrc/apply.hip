@@ -739,13 +739,16 @@ constexpr int kInterpWavesPerEUMax = sizeof(T) == 4 ? kInterpWavesPerEU<T, W, RE
 template <typename T, int W, bool REGEN>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T, W, REGEN>, kInterpWavesPerEUMax<T, W, REGEN>))) void k_interp(
     PlanArgs<T> a, cplx<T> *__restrict__ u, long long ustride, int B, int bofs, int l0, int l1) {
-    interp_body<T, W, REGEN>(a, u, ustride, B, bofs, l0, l1, blockIdx.x);
+    const int tiles = (a.N + kTileX - 1) / kTileX;
+    interp_body<T, W, REGEN>(a, u, ustride, B, bofs, l0, l1,
+                             chunked_tile(xcd_slot(blockIdx.x, gridDim.x), tiles));
 }
 
 template <typename T, int W, bool REGEN>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T, W, REGEN>, kInterpWavesPerEUMax<T, W, REGEN>))) void k_interp_multi(
     const InstArgs<T> *__restrict__ inst, const MultiTile *__restrict__ tiles) {
-    const MultiTile m = tiles[blockIdx.x];
+    // the table lists each instance's tiles in the chunked walk
+    const MultiTile m = tiles[xcd_slot(blockIdx.x, gridDim.x)];
     const InstArgs<T> I = load_inst(inst, m.inst);
     interp_body<T, W, REGEN>(I.a, I.u + (long long)m.b0 * I.a.N * I.a.N, (long long)I.a.N * I.a.N, m.nb, m.b0, 0,
                              I.a.L, m.tile);

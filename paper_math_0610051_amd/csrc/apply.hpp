@@ -19,6 +19,31 @@ constexpr int kRowLdsBytes = 32768;   // in-place FFT buffer of a row-stage work
 constexpr int kColLdsBytes = 32768;   // in-place FFT buffer of a column-stage workgroup
 constexpr int kColThreads = 512;      // workgroup size of the column stage
 constexpr int kInterpWidths[] = {4, 5, 6, 7, 8, 10, 12, 14, 16};
+constexpr int kXcds = 8;              // accelerator dies; workgroup i of a launch runs on die i % kXcds
+constexpr int kTileChunk = 8;         // interpolation tiles are walked in kTileChunk x kTileChunk squares
+
+// Workgroup id -> position in a list of n work items such that each die runs
+// one contiguous run of the list (die x gets items [x * n / 8 ...) in order).
+__host__ __device__ inline int xcd_slot(int bid, int n) {
+    const int q = n / kXcds, r = n % kXcds, x = bid % kXcds, s = bid / kXcds;
+    return x < r ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+}
+
+// Position li in the walk of a tiles x tiles grid of interpolation tiles ->
+// row-major tile index.  The walk covers bands of kTileChunk tile rows, each
+// band square by square, each square row by row: tiles that run together on
+// one die are neighbours in both directions, and the halos of their windows
+// are read from that die's L2.
+__host__ __device__ inline int chunked_tile(int li, int tiles) {
+    const int band = li / (kTileChunk * tiles);
+    const int hb = tiles - band * kTileChunk < kTileChunk ? tiles - band * kTileChunk : kTileChunk;
+    const int rem = li - band * kTileChunk * tiles;
+    const int c = rem / (hb * kTileChunk);
+    const int rc = rem - c * hb * kTileChunk;
+    const int wc = tiles - c * kTileChunk < kTileChunk ? tiles - c * kTileChunk : kTileChunk;
+    const int row = rc / wc, col = rc - row * wc;
+    return (band * kTileChunk + row) * tiles + c * kTileChunk + col;
+}
 
 // Per-instance arguments of the multi-instance kernels.
 template <typename T>

@@ -78,7 +78,7 @@ static fio_status build_state(MultiState &st, int n, const fio_plan_t *plans, co
         const int t = (P->N + kTileX - 1) / kTileX;
         for (int b0 = 0; b0 < B[i]; b0 += kInterpBatch)
             for (int k = 0; k < t * t; ++k)
-                tiles.push_back(MultiTile{i, k, b0, std::min(kInterpBatch, B[i] - b0)});
+                tiles.push_back(MultiTile{i, chunked_tile(k, t), b0, std::min(kInterpBatch, B[i] - b0)});
         lds_rows = std::max(lds_rows, P->lds_rows);
         lds_cols = std::max(lds_cols, P->lds_cols);
     }
