@@ -372,6 +372,22 @@ __device__ inline int stencil_origin(double m, double y, double k, double &u) {
 // the number of distinct residues, summed over the workgroup; the lowest
 // score wins, ties going to the smaller stride.  Lane sets whose cells spread
 // beyond 16 x 4 are not scored.  Contains one block barrier.
+// Kernel weight phi(z) = exp(beta (sqrt(1 - (2z/w)^2) - 1)) of the ES kernel.
+// In FP32 the hardware base-2 exponential and square root suffice: the
+// argument of the exponential lies in [-beta log2(e), 0] and 1 - (2z/w)^2 is
+// either at most 0 or at least 2^-23, so neither needs the range and
+// denormal handling of the library functions; their error (about one ulp)
+// is below that of the FP32 argument itself.
+template <typename T>
+__device__ __forceinline__ T es_weight(T z, T two_over_w, T beta) {
+    if constexpr (sizeof(T) == 4) {
+        const float u = z * two_over_w, s = 1.0f - u * u;
+        return s > 0.0f ? __builtin_amdgcn_exp2f(beta * 1.44269504f * (__builtin_amdgcn_sqrtf(s) - 1.0f)) : 0.0f;
+    } else {
+        return es_kernel<T>(z, two_over_w, beta);
+    }
+}
+
 constexpr int kPassXor[4] = {1, 2, 12, 24};  // generators of one ds_read_b128 lane set
 __device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int lane, int wave,
                                       unsigned long long *red2) {
@@ -552,8 +568,8 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         T w1[W], w2[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) {
-            w1[i] = es_kernel<T>(f1 - T(i), a.two_over_w, a.beta);
-            w2[i] = es_kernel<T>(f2 - T(i), a.two_over_w, a.beta);
+            w1[i] = es_weight<T>(f1 - T(i), a.two_over_w, a.beta);
+            w2[i] = es_weight<T>(f2 - T(i), a.two_over_w, a.beta);
         }
         // small stencils use the W x W products of the weights: one FMA per
         // window value instead of a product and a row sum per stencil row
@@ -572,7 +588,9 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         const int plane = F1 * S2;               // units of one rank-pair plane of the window
         const int ppr = kUnits / plane;          // planes staged per round
         const bool staged = ppr >= 1 && F1 <= m1 && F2 <= m2 && F1 * F2 <= kOff * kThreads;
-        const cplx<T> *gxp = a.gx + wd.gx_off + p * q;
+        // lanes beyond a ragged edge of the grid run the plane loop on point 0
+        // and window cell (0, 0), and their sums are never written
+        const cplx<T> *gxp = a.gx + wd.gx_off + (active ? p : 0) * q;
         const cplx<T> mod = cmake(cs, sn);
         const cplx<T> *G0 = a.G + (long long)bofs * a.G_stride + wd.G_off;
         if (staged) {
@@ -607,7 +625,7 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                     dst[k] = rr * S2 + cc;
                 }
             }
-            const int base = (j1 - J1) * S2 + (j2 - J2);
+            const int base = active ? (j1 - J1) * S2 + (j2 - J2) : 0;
             // Planes (b, tl), right-hand side major, are staged ppr at a time, so
             // one round serves several right-hand sides between two barriers.
             const int nplanes = B * qu;
@@ -631,7 +649,9 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                     }
                 }
                 __syncthreads();
-                if (active) {
+                // (b, tl, vb) stay uniform, so the accumulator of right-hand
+                // side vb is selected by scalar branches
+                {
                     int b = pb, tl = ptl;
                     for (int k2 = 0; k2 < np; ++k2) {
                         if (b != vb) {
@@ -706,7 +726,7 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                 }
                 __syncthreads();
             }
-            if (active) {
+            {
                 const cplx<T> mv = rotate_rhs<T>(mod, v);
                 FIO_ACC_ADD(acc, vb, mv);
             }
