@@ -440,6 +440,15 @@ __device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int l
     return F2 + best;
 }
 
+// a += b * c as four fused multiply-adds
+template <typename T>
+__device__ __forceinline__ void cfma4(cplx<T> &a, cplx<T> b, cplx<T> c) {
+    a.re = fma(b.re, c.re, a.re);
+    a.re = fma(-b.im, c.im, a.re);
+    a.im = fma(b.re, c.im, a.im);
+    a.im = fma(b.im, c.re, a.im);
+}
+
 // acc[vb] += mod * v, without floating-point contraction, so that every call
 // site rounds alike (a batch then equals a loop of single right-hand sides bit
 // for bit).
@@ -498,6 +507,8 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         // thread's point from the FP64 residual phase, into LDS after the
         // window ([t / CPU][thread] units; each thread reads only its own)
         cplx<T> *gxl = reinterpret_cast<cplx<T> *>(smem_raw + kInterpLdsBytes);
+        // the staged path reads gamma^x from LDS; larger ranks take the direct path
+        const bool gx_lds = REGEN || a.qmax <= kGxLdsMaxRank<T>;
         if constexpr (REGEN) {
             const double2 *zc = a.zcol + wd.zc_off;
             const double2 *zm = a.zmat + wd.zm_off;
@@ -585,82 +596,113 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         const int F1 = X1 - J1 + W, F2 = X2 - J2 + W;
         // the barrier in pick_row_stride also separates these reads of red from the next wedge's writes
         const int S2 = pick_row_stride(active, j1 - J1, j2 - J2, F2, lane, wave, red2);
-        const int plane = F1 * S2;               // units of one rank-pair plane of the window
-        const int ppr = kUnits / plane;          // planes staged per round
-        const bool staged = ppr >= 1 && F1 <= m1 && F2 <= m2 && F1 * F2 <= kOff * kThreads;
+        // The window of one rank-pair plane is F1 rows of S2 units (unit e =
+        // rr * S2 + cc holds cell (J1 + rr, J2 + cc)), padded to whole 64-unit
+        // wave chunks.  Rounds of planes are copied from G straight into LDS by
+        // global_load_lds (lane i of a wave writes unit 64 c + i of chunk c):
+        // with two buffers the next round's copies run under the current
+        // round's interpolation, with one a round is copied, then used.
+        const int units = F1 * S2;
+        const int planeP = (units + 63) & ~63;
+        const int nbuf = 2 * planeP <= kUnits ? 2 : 1;
+        const int bufU = kUnits / nbuf / 64 * 64;
+        const int ppr = bufU / planeP;           // planes per round
+        const bool staged = gx_lds && ppr >= 1 && F1 <= m1 && F2 <= m2 && units <= kOff * kThreads;
         // lanes beyond a ragged edge of the grid run the plane loop on point 0
         // and window cell (0, 0), and their sums are never written
         const cplx<T> *gxp = a.gx + wd.gx_off + (active ? p : 0) * q;
         const cplx<T> mod = cmake(cs, sn);
         const cplx<T> *G0 = a.G + (long long)bofs * a.G_stride + wd.G_off;
         if (staged) {
-            // source offsets (rank 0) and window positions of this thread's
-            // cells, in column-major cell order (G is [j2][j1][rank])
-            // J1 > -W and J1 + F1 <= 2 m1 (likewise for axis 2), so one
-            // conditional wrap brings every window cell onto the grid
-            int off[kOff], dst[kOff];
+            // source offsets (rank 0) of this thread's units tid + k kThreads;
+            // padding units copy cell 0 of the plane.  J1 > -W and J1 + F1 <=
+            // 2 m1 (likewise for axis 2), so one conditional wrap brings every
+            // window cell onto the grid (G is [j2][j1][rank])
+            int off[kOff];
             const int c0 = J2 < 0 ? J2 + m2 : (J2 >= m2 ? J2 - m2 : J2);
             const int r0 = J1 < 0 ? J1 + m1 : (J1 >= m1 ? J1 - m1 : J1);
-            const float rF1 = 1.0f / (float)F1;
+            const float rS2 = 1.0f / (float)S2;
 #pragma unroll
             for (int k = 0; k < kOff; ++k) {
                 const int e = tid + k * kThreads;
-                off[k] = -1;
-                dst[k] = 0;
-                if (e < F1 * F2) {
-                    // e / F1 for e < 2^11: the float quotient is off by at most one
-                    int cc = (int)((float)e * rF1);
-                    if (cc * F1 > e)
-                        --cc;
-                    else if ((cc + 1) * F1 <= e)
-                        ++cc;
-                    const int rr = e - cc * F1;
-                    int gr = r0 + rr;
-                    if (gr >= m1)
-                        gr -= m1;
-                    int gc = c0 + cc;
-                    if (gc >= m2)
-                        gc -= m2;
-                    off[k] = (gc * m1 + gr) * q;
-                    dst[k] = rr * S2 + cc;
+                off[k] = 0;
+                if (e < units) {
+                    // e / S2 for e < 2^11: the float quotient is off by at most one
+                    int rr = (int)((float)e * rS2);
+                    if (rr * S2 > e)
+                        --rr;
+                    else if ((rr + 1) * S2 <= e)
+                        ++rr;
+                    const int cc = e - rr * S2;
+                    if (cc < F2) {
+                        int gr = r0 + rr;
+                        if (gr >= m1)
+                            gr -= m1;
+                        int gc = c0 + cc;
+                        if (gc >= m2)
+                            gc -= m2;
+                        off[k] = (gc * m1 + gr) * q;
+                    }
                 }
             }
             const int base = active ? (j1 - J1) * S2 + (j2 - J2) : 0;
-            // Planes (b, tl), right-hand side major, are staged ppr at a time, so
-            // one round serves several right-hand sides between two barriers.
+            // stored gamma^x rows of the tile's points, copied into LDS
+            // ([t / CPU][thread] units) with the first round; the interpolation
+            // then never waits on a global load of its own
+            if constexpr (!REGEN) {
+                for (int tl = 0; tl < qu; ++tl)
+                    __builtin_amdgcn_global_load_lds(
+                        reinterpret_cast<const void *>(gxp + tl * CPU),
+                        (__attribute__((address_space(3))) void *)(reinterpret_cast<U *>(gxl) + tl * kThreads +
+                                                                    wave * 64),
+                        16, 0, 0);
+            }
+            // Planes (b, tl), right-hand side major, go ppr to a round, so one
+            // round serves several right-hand sides between two barriers.
             const int nplanes = B * qu;
-            int pb = 0, ptl = 0;         // (b, tl) of the round's first plane
+            const int nrounds = (nplanes + ppr - 1) / ppr;
+            int sb = 0, stl = 0;         // (b, tl) of the next plane to copy
+            int cb = 0, ctl = 0;         // (b, tl) of the next plane to interpolate
             cplx<T> v = cmake<T>(0, 0);  // partial sum of right-hand side vb
             int vb = 0;
-            for (int p0 = 0; p0 < nplanes; p0 += ppr) {
-                const int np = min(ppr, nplanes - p0);
-                {
-                    int b = pb, tl = ptl;
-                    for (int k2 = 0; k2 < np; ++k2) {
-                        const cplx<T> *G = G0 + (long long)b * a.G_stride + tl * CPU;
+            for (int r = 0; r <= nrounds; ++r) {
+                // copy round r (two buffers: while round r - 1 is interpolated)
+                const bool copy_now = r < nrounds && (nbuf == 2 || r == 0);
+                for (int pass = 0; pass < 2; ++pass) {
+                    if (pass == 0 ? copy_now : (nbuf == 1 && r > 0 && r < nrounds)) {
+                        if (pass == 1)
+                            __syncthreads();  // one buffer: round r - 1 has been read
+                        const int np = min(ppr, nplanes - r * ppr);
+                        U *dst = win + (r & (nbuf - 1)) * bufU + wave * 64;
+                        for (int k2 = 0; k2 < np; ++k2) {
+                            const cplx<T> *G = G0 + (long long)sb * a.G_stride + stl * CPU;
 #pragma unroll
-                        for (int k = 0; k < kOff; ++k)
-                            if (off[k] >= 0)
-                                win[k2 * plane + dst[k]] = *reinterpret_cast<const U *>(G + off[k]);
-                        if (++tl == qu) {
-                            tl = 0;
-                            ++b;
+                            for (int k = 0; k < kOff; ++k)
+                                if (wave * 64 + k * kThreads < units)
+                                    __builtin_amdgcn_global_load_lds(
+                                        reinterpret_cast<const void *>(G + off[k]),
+                                        (__attribute__((address_space(3))) void *)(dst + k2 * planeP + k * kThreads), 16,
+                                        0, 0);
+                            if (++stl == qu) {
+                                stl = 0;
+                                ++sb;
+                            }
                         }
                     }
-                }
-                __syncthreads();
-                // (b, tl, vb) stay uniform, so the accumulator of right-hand
-                // side vb is selected by scalar branches
-                {
-                    int b = pb, tl = ptl;
+                    if (pass == 1 || r == 0)
+                        break;
+                    // interpolate round r - 1; (b, tl, vb) stay uniform, so the
+                    // accumulator of right-hand side vb is selected by scalar branches
+                    const int np = min(ppr, nplanes - (r - 1) * ppr);
+                    const U *src = win + ((r - 1) & (nbuf - 1)) * bufU + base;
                     for (int k2 = 0; k2 < np; ++k2) {
-                        if (b != vb) {
+                        if (cb != vb) {
                             const cplx<T> mv = rotate_rhs<T>(mod, v);
                             FIO_ACC_ADD(acc, vb, mv);
                             v = cmake<T>(0, 0);
-                            vb = b;
+                            vb = cb;
                         }
-                        const U *pw = win + k2 * plane + base;
+                        const U *pw = src + k2 * planeP;
                         U sum;
                         if constexpr (CPU == 2)
                             sum = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -708,22 +750,19 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                                 sum.w += w1[i1] * rs.w;
                             }
                         }
-                        const U gx = REGEN ? reinterpret_cast<const U *>(gxl)[tl * kThreads + tid]
-                                           : *reinterpret_cast<const U *>(gxp + tl * CPU);
-                        cfma(v, cmake<T>(gx.x, gx.y), cmake<T>(sum.x, sum.y));
+                        const U gx = reinterpret_cast<const U *>(gxl)[ctl * kThreads + tid];
+                        cfma4(v, cmake<T>(gx.x, gx.y), cmake<T>(sum.x, sum.y));
                         if constexpr (CPU == 2)
-                            cfma(v, cmake<T>(gx.z, gx.w), cmake<T>(sum.z, sum.w));
-                        if (++tl == qu) {
-                            tl = 0;
-                            ++b;
+                            cfma4(v, cmake<T>(gx.z, gx.w), cmake<T>(sum.z, sum.w));
+                        if (++ctl == qu) {
+                            ctl = 0;
+                            ++cb;
                         }
                     }
                 }
-                ptl += np;
-                while (ptl >= qu) {
-                    ptl -= qu;
-                    ++pb;
-                }
+                // this wave's copies have landed; after the barrier every wave's
+                // have, and the buffer read in this round may be overwritten
+                __builtin_amdgcn_s_waitcnt(0);
                 __syncthreads();
             }
             {
@@ -786,7 +825,7 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
 // FP64 keeps the compiler's choice.
 template <typename T, int W, bool REGEN>
 constexpr int kInterpWavesPerEU =
-    sizeof(T) == 4 ? (W <= 5 ? 4 : (W == 6 ? 3 : 2)) - (REGEN ? 1 : 0) : 1;
+    sizeof(T) == 4 ? (W <= 5 ? 3 : (W == 6 ? 3 : 2)) - (REGEN ? 1 : 0) : 1;
 template <typename T, int W, bool REGEN>
 constexpr int kInterpWavesPerEUMax = sizeof(T) == 4 ? kInterpWavesPerEU<T, W, REGEN> : 2;
 
@@ -837,11 +876,12 @@ PlanArgs<T> make_args(const fio_plan_s *P) {
     return a;
 }
 
-// Dynamic LDS of the interpolation: the window, plus the regenerated
-// gamma^x of the tile's points (kThreads x qmax complex) in FIO_FACTORS_REGEN.
+// Dynamic LDS of the interpolation: the window buffers, plus gamma^x of the
+// tile's points (kThreads x qmax complex; regenerated in FIO_FACTORS_REGEN,
+// copied from the stored factors otherwise, when qmax is small enough).
 template <typename T>
-size_t interp_lds_bytes(bool regen, int qmax) {
-    return kInterpLdsBytes + (regen ? (size_t)kThreads * qmax * sizeof(cplx<T>) : 0);
+size_t interp_lds_bytes(int qmax) {
+    return kInterpLdsBytes + interp_gx_lds_bytes<T>(qmax);
 }
 
 template <typename T, int W>
@@ -849,11 +889,11 @@ static hipError_t launch_interp_w(const fio_plan_s *P, const PlanArgs<T> &a, cpl
                                   int bofs, int l0, int l1, hipStream_t s) {
     const int tiles = (P->N + kTileX - 1) / kTileX;
     if (P->regen)
-        k_interp<T, W, true><<<(unsigned)(tiles * tiles), kThreads, interp_lds_bytes<T>(true, P->qmax), s>>>(
+        k_interp<T, W, true><<<(unsigned)(tiles * tiles), kThreads, interp_lds_bytes<T>(P->qmax), s>>>(
             a, u, ustride, B, bofs, l0, l1);
     else
-        k_interp<T, W, false><<<(unsigned)(tiles * tiles), kThreads, kInterpLdsBytes, s>>>(a, u, ustride, B, bofs,
-                                                                                            l0, l1);
+        k_interp<T, W, false><<<(unsigned)(tiles * tiles), kThreads, interp_lds_bytes<T>(P->qmax), s>>>(
+            a, u, ustride, B, bofs, l0, l1);
     return hipGetLastError();
 }
 
@@ -935,13 +975,21 @@ static hipError_t apply_t(fio_plan_s *P, int B, const void *fhat, void *u, hipSt
 template <typename T, int... Ws>
 static hipError_t set_interp_lds_limits() {
     hipError_t e = hipSuccess;
-    // the regenerating variants take the window plus kThreads x kRegenMaxRank complex
+    // the window plus up to kThreads x kGxLdsMaxRank complex of gamma^x
     ((e = e != hipSuccess ? e
                           : hipFuncSetAttribute(reinterpret_cast<const void *>(&k_interp<T, Ws, true>),
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes)),
      ...);
     ((e = e != hipSuccess ? e
                           : hipFuncSetAttribute(reinterpret_cast<const void *>(&k_interp_multi<T, Ws, true>),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes)),
+     ...);
+    ((e = e != hipSuccess ? e
+                          : hipFuncSetAttribute(reinterpret_cast<const void *>(&k_interp<T, Ws, false>),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes)),
+     ...);
+    ((e = e != hipSuccess ? e
+                          : hipFuncSetAttribute(reinterpret_cast<const void *>(&k_interp_multi<T, Ws, false>),
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes)),
      ...);
     return e;
@@ -984,7 +1032,7 @@ static void launch_multi_w(const MultiLaunch &ml, hipStream_t s) {
         if (ml.regen)
             k_interp_multi<T, W, true><<<ml.ntiles, kThreads, ml.lds_interp, s>>>(I, ml.tiles);
         else
-            k_interp_multi<T, W, false><<<ml.ntiles, kThreads, kInterpLdsBytes, s>>>(I, ml.tiles);
+            k_interp_multi<T, W, false><<<ml.ntiles, kThreads, ml.lds_interp, s>>>(I, ml.tiles);
     }
 }
 

@@ -11,7 +11,7 @@ constexpr int kThreads = 256;       // workgroup size of every apply kernel
 constexpr int kInterpBatch = 8;     // right-hand sides per interpolation launch
 constexpr int kTileX = 16;          // interpolation tile: kTileX x kTileX output points per workgroup
 constexpr int kRegenMaxRank = 16;      // padded rank bound of FIO_FACTORS_REGEN (FP32; half in FP64)
-constexpr int kInterpLdsBytes = 38912;  // LDS windows (rank planes of several right-hand sides) per interpolation workgroup: four per CU
+constexpr int kInterpLdsBytes = 36864;  // LDS window buffers (rank planes of several right-hand sides) per interpolation workgroup
 constexpr int kMaxLdsBytes = 131072;  // largest dynamic LDS request of any apply kernel
 constexpr int kFftThreads = 512;     // workgroup size of the two FFT stages
 constexpr int kFftWavesPerEU = 4;    // register budget: two FFT workgroups per CU overlap load, transform and store
@@ -19,6 +19,15 @@ constexpr int kRowLdsBytes = 32768;   // in-place FFT buffer of a row-stage work
 constexpr int kColLdsBytes = 32768;   // in-place FFT buffer of a column-stage workgroup
 constexpr int kColThreads = 512;      // workgroup size of the column stage
 constexpr int kInterpWidths[] = {4, 5, 6, 7, 8, 10, 12, 14, 16};
+// gamma^x of a workgroup's points (kThreads x padded rank complex, at most
+// 96 KB) follows the window in LDS when the padded rank is at most this; plans
+// of larger rank interpolate straight from global memory
+template <typename T>
+constexpr int kGxLdsMaxRank = sizeof(T) == 4 ? 48 : 24;
+template <typename T>
+inline size_t interp_gx_lds_bytes(int qmax) {
+    return qmax <= kGxLdsMaxRank<T> ? (size_t)kThreads * qmax * 2 * sizeof(T) : 0;
+}
 constexpr int kXcds = 8;              // accelerator dies; workgroup i of a launch runs on die i % kXcds
 constexpr int kTileChunk = 8;         // interpolation tiles are walked in kTileChunk x kTileChunk squares
 

@@ -102,11 +102,11 @@ static fio_status build_state(MultiState &st, int n, const fio_plan_t *plans, co
     st.ml.lds_rows = lds_rows;
     st.ml.lds_cols = lds_cols;
     st.ml.regen = plans[0]->regen;
-    {
-        int qmax = 0;
-        for (int i = 0; i < n; ++i)
-            qmax = std::max(qmax, plans[i]->qmax);
-        st.ml.lds_interp = kInterpLdsBytes + (st.ml.regen ? (size_t)kThreads * qmax * plans[0]->esize : 0);
+    // window plus the largest gamma^x block an instance keeps in LDS
+    for (int i = 0; i < n; ++i) {
+        const size_t gx = plans[i]->precision == FIO_F64 ? interp_gx_lds_bytes<double>(plans[i]->qmax)
+                                                         : interp_gx_lds_bytes<float>(plans[i]->qmax);
+        st.ml.lds_interp = std::max(st.ml.lds_interp, kInterpLdsBytes + gx);
     }
     // capture the three launches once
     FIO_HIP_TRY(hipStreamCreateWithFlags(&st.cap, hipStreamNonBlocking));
