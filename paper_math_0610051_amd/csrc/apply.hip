@@ -457,10 +457,13 @@ __device__ __forceinline__ cplx<T> rotate_rhs(const cplx<T> &mod, const cplx<T> 
 #pragma clang fp contract(off)
     return cmake<T>(mod.re * v.re - mod.im * v.im, mod.re * v.im + mod.im * v.re);
 }
-// acc[vb] += mv for a run-time vb, by predication over the registers of acc
+// acc[vb] += mv for a uniform run-time vb: one branch per register of acc
+// (the empty volatile asm keeps the compiler from turning the branches into
+// selects over all of acc)
 #define FIO_ACC_ADD(acc, vb, mv)                          \
     do {                                                  \
         _Pragma("unroll") for (int bb_ = 0; bb_ < kInterpBatch; ++bb_) if (bb_ == (vb)) { \
+            asm volatile("");                             \
             acc[bb_].re += (mv).re;                       \
             acc[bb_].im += (mv).im;                       \
         }                                                 \
@@ -471,7 +474,8 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                                             int bofs, int l0, int l1, int tile) {
     using U = typename Unit16<T>::type;
     constexpr int CPU = 16 / (int)sizeof(cplx<T>);  // complex per 16-byte unit (rank pair / single rank)
-    constexpr int kUnits = kInterpLdsBytes / 16;     // window capacity in units
+    const int win_bytes = interp_window_bytes<T>(a.qmax);
+    const int kUnits = win_bytes / 16;               // window capacity in units
     constexpr int kOff = 6;                          // staged cells per thread: windows up to 1536 cells
     extern __shared__ unsigned char smem_raw[];
     U *win = reinterpret_cast<U *>(smem_raw);
@@ -506,7 +510,7 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         // FIO_FACTORS_REGEN: gamma^x(x, t) = sum_c A(x, C_c) Z(c, t) for this
         // thread's point from the FP64 residual phase, into LDS after the
         // window ([t / CPU][thread] units; each thread reads only its own)
-        cplx<T> *gxl = reinterpret_cast<cplx<T> *>(smem_raw + kInterpLdsBytes);
+        cplx<T> *gxl = reinterpret_cast<cplx<T> *>(smem_raw + win_bytes);
         // the staged path reads gamma^x from LDS; larger ranks take the direct path
         const bool gx_lds = REGEN || a.qmax <= kGxLdsMaxRank<T>;
         if constexpr (REGEN) {
@@ -840,8 +844,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInter
 template <typename T, int W, bool REGEN>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kInterpWavesPerEU<T, W, REGEN>, kInterpWavesPerEUMax<T, W, REGEN>))) void k_interp_multi(
     const InstArgs<T> *__restrict__ inst, const MultiTile *__restrict__ tiles) {
-    // the table lists each instance's tiles in the chunked walk
-    const MultiTile m = tiles[xcd_slot(blockIdx.x, gridDim.x)];
+    // the table interleaves one stream of tiles per die (slot i runs on die
+    // i % kXcds); padding entries have no right-hand sides
+    const MultiTile m = tiles[blockIdx.x];
+    if (m.nb == 0)
+        return;
     const InstArgs<T> I = load_inst(inst, m.inst);
     interp_body<T, W, REGEN>(I.a, I.u + (long long)m.b0 * I.a.N * I.a.N, (long long)I.a.N * I.a.N, m.nb, m.b0, 0,
                              I.a.L, m.tile);
@@ -881,7 +888,7 @@ PlanArgs<T> make_args(const fio_plan_s *P) {
 // copied from the stored factors otherwise, when qmax is small enough).
 template <typename T>
 size_t interp_lds_bytes(int qmax) {
-    return kInterpLdsBytes + interp_gx_lds_bytes<T>(qmax);
+    return (size_t)interp_window_bytes<T>(qmax) + interp_gx_lds_bytes<T>(qmax);
 }
 
 template <typename T, int W>

@@ -11,7 +11,9 @@ constexpr int kThreads = 256;       // workgroup size of every apply kernel
 constexpr int kInterpBatch = 8;     // right-hand sides per interpolation launch
 constexpr int kTileX = 16;          // interpolation tile: kTileX x kTileX output points per workgroup
 constexpr int kRegenMaxRank = 16;      // padded rank bound of FIO_FACTORS_REGEN (FP32; half in FP64)
-constexpr int kInterpLdsBytes = 36864;  // LDS window buffers (rank planes of several right-hand sides) per interpolation workgroup
+constexpr int kInterpLdsTarget = 53248;  // interpolation LDS (window + gamma^x) per workgroup: three per CU
+constexpr int kInterpWindowMax = 36864;  // LDS window buffers (rank planes of several right-hand sides)
+constexpr int kInterpWindowMin = 16384;
 constexpr int kMaxLdsBytes = 131072;  // largest dynamic LDS request of any apply kernel
 constexpr int kFftThreads = 512;     // workgroup size of the two FFT stages
 constexpr int kFftWavesPerEU = 4;    // register budget: two FFT workgroups per CU overlap load, transform and store
@@ -25,8 +27,14 @@ constexpr int kInterpWidths[] = {4, 5, 6, 7, 8, 10, 12, 14, 16};
 template <typename T>
 constexpr int kGxLdsMaxRank = sizeof(T) == 4 ? 48 : 24;
 template <typename T>
-inline size_t interp_gx_lds_bytes(int qmax) {
-    return qmax <= kGxLdsMaxRank<T> ? (size_t)kThreads * qmax * 2 * sizeof(T) : 0;
+__host__ __device__ inline int interp_gx_lds_bytes(int qmax) {
+    return qmax <= kGxLdsMaxRank<T> ? kThreads * qmax * 2 * (int)sizeof(T) : 0;
+}
+// window bytes: what the target leaves beside gamma^x, within [min, max]
+template <typename T>
+__host__ __device__ inline int interp_window_bytes(int qmax) {
+    const int w = kInterpLdsTarget - interp_gx_lds_bytes<T>(qmax);
+    return w > kInterpWindowMax ? kInterpWindowMax : (w < kInterpWindowMin ? kInterpWindowMin : w / 1024 * 1024);
 }
 constexpr int kXcds = 8;              // accelerator dies; workgroup i of a launch runs on die i % kXcds
 constexpr int kTileChunk = 8;         // interpolation tiles are walked in kTileChunk x kTileChunk squares

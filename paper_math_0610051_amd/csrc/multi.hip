@@ -74,13 +74,41 @@ static fio_status build_state(MultiState &st, int n, const fio_plan_t *plans, co
         for (int b = 0; b < B[i]; ++b)
             for (const ColItem &c : P->cols)
                 cols.push_back(MultiColItem{i, b, c});
-        // interpolation tiles in groups of up to kInterpBatch right-hand sides
-        const int t = (P->N + kTileX - 1) / kTileX;
-        for (int b0 = 0; b0 < B[i]; b0 += kInterpBatch)
-            for (int k = 0; k < t * t; ++k)
-                tiles.push_back(MultiTile{i, chunked_tile(k, t), b0, std::min(kInterpBatch, B[i] - b0)});
         lds_rows = std::max(lds_rows, P->lds_rows);
         lds_cols = std::max(lds_cols, P->lds_cols);
+    }
+    // Interpolation tiles, in groups of up to kInterpBatch right-hand sides.
+    // Workgroup i of a launch runs on die i % kXcds.  Each instance's tiles are
+    // cut into runs of 64 along the chunked walk (8 x 8-tile squares); the runs
+    // are dealt, heaviest instance first, to the die stream of least work so
+    // far (work ~ wedges x right-hand sides per tile), and the streams are
+    // interleaved so that slot i holds die i % kXcds's next tile: each die
+    // then walks whole squares (the halos of neighbouring tiles meet in its
+    // L2) while the dies get equal work.  Streams that run out are padded
+    // with empty entries (nb = 0).
+    {
+        std::vector<std::vector<MultiTile>> stream(kXcds);
+        std::vector<double> work(kXcds, 0.0);
+        for (int i : order) {
+            const fio_plan_s *P = plans[i];
+            const int t = (P->N + kTileX - 1) / kTileX;
+            for (int b0 = 0; b0 < B[i]; b0 += kInterpBatch) {
+                const int nb = std::min(kInterpBatch, B[i] - b0);
+                for (int k0 = 0; k0 < t * t; k0 += 64) {
+                    const int k1 = std::min(t * t, k0 + 64);
+                    const int x = (int)(std::min_element(work.begin(), work.end()) - work.begin());
+                    for (int k = k0; k < k1; ++k)
+                        stream[x].push_back(MultiTile{i, chunked_tile(k, t), b0, nb});
+                    work[x] += (double)(k1 - k0) * P->L * nb;
+                }
+            }
+        }
+        size_t longest = 0;
+        for (const auto &v : stream)
+            longest = std::max(longest, v.size());
+        for (size_t k = 0; k < longest; ++k)
+            for (int x = 0; x < kXcds; ++x)
+                tiles.push_back(k < stream[x].size() ? stream[x][k] : MultiTile{0, 0, 0, 0});
     }
     const size_t isz = inst_args_size(plans[0]->precision);
     FIO_HIP_TRY(hipMalloc(&st.d_inst, isz * n));
@@ -102,11 +130,13 @@ static fio_status build_state(MultiState &st, int n, const fio_plan_t *plans, co
     st.ml.lds_rows = lds_rows;
     st.ml.lds_cols = lds_cols;
     st.ml.regen = plans[0]->regen;
-    // window plus the largest gamma^x block an instance keeps in LDS
+    // the largest window + gamma^x an instance uses
     for (int i = 0; i < n; ++i) {
-        const size_t gx = plans[i]->precision == FIO_F64 ? interp_gx_lds_bytes<double>(plans[i]->qmax)
-                                                         : interp_gx_lds_bytes<float>(plans[i]->qmax);
-        st.ml.lds_interp = std::max(st.ml.lds_interp, kInterpLdsBytes + gx);
+        const int q = plans[i]->qmax;
+        const size_t b = plans[i]->precision == FIO_F64
+                             ? (size_t)interp_window_bytes<double>(q) + interp_gx_lds_bytes<double>(q)
+                             : (size_t)interp_window_bytes<float>(q) + interp_gx_lds_bytes<float>(q);
+        st.ml.lds_interp = std::max(st.ml.lds_interp, b);
     }
     // capture the three launches once
     FIO_HIP_TRY(hipStreamCreateWithFlags(&st.cap, hipStreamNonBlocking));
