@@ -414,7 +414,7 @@ __device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int l
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             key |= __shfl_xor(key, kPassXor[j]);
-        const int score = wide ? 0 : ncell - __popc(key);  // 0..15 per quarter-wave
+        const int score = wide ? 0 : ncell - __popc(key);  // 0..15 per lane set
         packed |= (unsigned long long)score << (8 * k);
     }
     // 8-bit fields: at most 4 x 4 x 15 = 240 per candidate over the workgroup;
@@ -819,17 +819,14 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
     }
 }
 
-// FP32: at most 168 VGPRs, so that three workgroups share a SIMD (the
-// compiler otherwise hoists whole stencil planes into registers); FP64 keeps
-// the default budget, which it needs to avoid spills.
-// Occupancy targets of the FP32 interpolation: four waves per SIMD (128
-// VGPRs, matching the four workgroups per CU that the 38 KB window allows)
-// for widths up to 5, three for width 6 and two for wider stencils, whose
-// planes need more registers, and one fewer when gamma^x is regenerated;
-// FP64 keeps the compiler's choice.
+// Occupancy targets of the FP32 interpolation: three waves per SIMD (168
+// VGPRs, matching the three workgroups per CU that the window and gamma^x
+// rows fit in LDS) for widths up to 6, two for wider stencils, whose planes
+// need more registers, and one fewer when gamma^x is regenerated.  The cap
+// also keeps the compiler from hoisting whole stencil planes into registers.
+// FP64 keeps the compiler's choice, which it needs to avoid spills.
 template <typename T, int W, bool REGEN>
-constexpr int kInterpWavesPerEU =
-    sizeof(T) == 4 ? (W <= 5 ? 3 : (W == 6 ? 3 : 2)) - (REGEN ? 1 : 0) : 1;
+constexpr int kInterpWavesPerEU = sizeof(T) == 4 ? (W <= 6 ? 3 : 2) - (REGEN ? 1 : 0) : 1;
 template <typename T, int W, bool REGEN>
 constexpr int kInterpWavesPerEUMax = sizeof(T) == 4 ? kInterpWavesPerEU<T, W, REGEN> : 2;
 
