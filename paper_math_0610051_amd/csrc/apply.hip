@@ -826,7 +826,8 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
 // also keeps the compiler from hoisting whole stencil planes into registers.
 // FP64 keeps the compiler's choice, which it needs to avoid spills.
 template <typename T, int W, bool REGEN>
-constexpr int kInterpWavesPerEU = sizeof(T) == 4 ? (W <= 6 ? 3 : 2) - (REGEN ? 1 : 0) : 1;
+constexpr int kInterpWavesPerEU =
+    sizeof(T) == 4 ? (W <= 5 ? 3 : (W == 6 ? 3 : 2)) - (REGEN ? 1 : 0) : 1;
 template <typename T, int W, bool REGEN>
 constexpr int kInterpWavesPerEUMax = sizeof(T) == 4 ? kInterpWavesPerEU<T, W, REGEN> : 2;
 
