@@ -148,6 +148,21 @@ fio_status fio_plan(int N, const fio_phase *phase, const fio_amplitude *amp, dou
 fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, double tol,
                        const fio_options *opt /* nullable */, fio_plan_t *out);
 
+/* Plan files.  fio_plan_save writes the plan's build inputs (N, phase, tol,
+ * options) and, per wedge, the compressed factors of its randomized
+ * separation (Section 3.2, eq. (probnewfac): sampled columns and rows,
+ * Z = V S^-1, U_[R]^+, rank and error estimate) to a little-endian binary file
+ * with a checksum; the caller owns the path.  fio_plan_load rebuilds the
+ * geometry, checks it against the file and evaluates the factors on the
+ * current device, skipping the sampling and the eigen-solves: the loaded plan
+ * applies bit for bit like the saved one and is owned by the caller (release
+ * with fio_destroy).  FIO_ENOTSUP for a plan with learned factors (save its
+ * network with fio_learned_save instead); FIO_EINVAL for an unreadable,
+ * truncated or corrupted file, or one whose geometry this library does not
+ * reproduce. */
+fio_status fio_plan_save(fio_plan_t plan, const char *path);
+fio_status fio_plan_load(const char *path, fio_plan_t *out);
+
 /* u = L fhat for one right-hand side (Section 3.4, eq. (dfioalgo)). */
 fio_status fio_apply(fio_plan_t plan, const void *fhat, void *u, void *stream);
 

@@ -51,6 +51,12 @@ static void drop_events(fio_plan_s *P) {
     P->prof_events.clear();
 }
 
+// unique per plan made in this process (built or loaded)
+static unsigned long long next_plan_serial() {
+    static std::atomic<unsigned long long> next{1};
+    return next++;
+}
+
 static void free_plan(fio_plan_s *P) {
     if (!P)
         return;
@@ -141,8 +147,7 @@ fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, 
     fio_plan_s *P = new (std::nothrow) fio_plan_s();
     if (!P)
         return (set_error("host allocation failed"), FIO_ENOMEM);
-    static std::atomic<unsigned long long> next_serial{1};
-    P->serial = next_serial++;
+    P->serial = next_plan_serial();
     P->N = N;
     P->phase.kind = phase->kind;
     std::memcpy(P->phase.p, phase->p, sizeof(P->phase.p));
@@ -169,6 +174,44 @@ fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, 
 
 fio_status fio_plan(int N, const fio_phase *phase, const fio_amplitude *amp, double tol, fio_plan_t *out) {
     return fio_plan_ex(N, phase, amp, tol, nullptr, out);
+}
+
+fio_status fio_plan_save(fio_plan_t plan, const char *path) {
+    set_error("");
+    if (!plan || !path)
+        return (set_error("null argument"), FIO_EINVAL);
+    try {
+        return save_plan(plan, path);
+    } catch (const std::bad_alloc &) {
+        return (set_error("host allocation failed"), FIO_ENOMEM);
+    }
+}
+
+fio_status fio_plan_load(const char *path, fio_plan_t *out) {
+    set_error("");
+    if (!path || !out)
+        return (set_error("null argument"), FIO_EINVAL);
+    *out = nullptr;
+    fio_plan_s *P = new (std::nothrow) fio_plan_s();
+    if (!P)
+        return (set_error("host allocation failed"), FIO_ENOMEM);
+    P->serial = next_plan_serial();
+    fio_status st;
+    try {
+        st = load_plan(P, path);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        st = FIO_ENOMEM;
+    } catch (...) {
+        set_error("unexpected host exception while loading the plan");
+        st = FIO_EDEVICE;
+    }
+    if (st != FIO_OK) {
+        free_plan(P);
+        return st;
+    }
+    *out = P;
+    return FIO_OK;
 }
 
 static fio_status apply_common(fio_plan_t P, int l0, int l1, int B, const void *fhat, void *u, void *stream) {

@@ -16,6 +16,7 @@
 //      FP64 and stored in the plan's precision.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <map>
 
@@ -1079,6 +1080,281 @@ static fio_status plan_learned(fio_plan_s *P, LearnedModel *net, const double2 *
             *ok = false;
     }
     return store_factors<float>(P, d_xcoef, false);
+}
+
+// ---------------------------------------------------------------------------
+// Plan files.  A plan is saved as its build inputs (N, phase, tol, options)
+// and, per wedge, the compressed factors of its randomized separation: the
+// sampled columns C and rows R, Z = V S^-1 and U_[R]^+ (eq. (probnewfac)),
+// the rank and the error estimate.  Loading rebuilds the geometry (a
+// deterministic function of N and the options), checks it against the file
+// and evaluates gamma^x and gamma^xi on the device from the saved factors,
+// exactly as a fresh build stores them, so a loaded plan applies bit for bit
+// like the plan that was saved; only the sampling and the eigen-solves of
+// the separation are skipped.  Little-endian binary with an FNV-1a checksum.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr char kPlanMagic[8] = {'F', 'I', 'O', 'P', 'L', 'A', 'N', '1'};
+constexpr uint32_t kPlanVersion = 1;
+
+struct PlanWriter {
+    FILE *f;
+    uint64_t h = 1469598103934665603ull;
+    bool ok = true;
+    void raw(const void *p, size_t n) {
+        if (!ok)
+            return;
+        ok = std::fwrite(p, 1, n, f) == n;
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; ++i)
+            h = (h ^ c[i]) * 1099511628211ull;
+    }
+    template <typename V>
+    void put(V v) {
+        raw(&v, sizeof v);
+    }
+    template <typename V>
+    void vec(const std::vector<V> &v) {
+        put<int64_t>((int64_t)v.size());
+        if (!v.empty())
+            raw(v.data(), v.size() * sizeof(V));
+    }
+};
+
+struct PlanReader {
+    FILE *f;
+    uint64_t h = 1469598103934665603ull;
+    bool ok = true;
+    void raw(void *p, size_t n) {
+        if (!ok)
+            return;
+        ok = std::fread(p, 1, n, f) == n;
+        if (!ok)
+            return;
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; ++i)
+            h = (h ^ c[i]) * 1099511628211ull;
+    }
+    template <typename V>
+    V get() {
+        V v{};
+        raw(&v, sizeof v);
+        return v;
+    }
+    // a vector of at most `limit` elements
+    template <typename V>
+    bool vec(std::vector<V> &v, int64_t limit) {
+        const int64_t n = get<int64_t>();
+        if (!ok || n < 0 || n > limit)
+            return ok = false;
+        v.resize((size_t)n);
+        if (n)
+            raw(v.data(), (size_t)n * sizeof(V));
+        return ok;
+    }
+};
+
+struct SavedWedge {
+    int32_t members = 0, q = 0, qpad = 0, r = 0, attempts = 0;
+    double sep_err = 0;
+    std::vector<int32_t> C;
+    std::vector<int64_t> R;
+    std::vector<zd> Z, Pinv;
+};
+}  // namespace
+
+fio_status save_plan(const fio_plan_s *P, const char *path) {
+    if (P->factor_mode == FIO_FACTORS_LEARNED)
+        return (set_error("a plan with learned factors is kept by saving its network (fio_learned_save)"),
+                FIO_ENOTSUP);
+    FILE *f = std::fopen(path, "wb");
+    if (!f)
+        return (set_error(std::string("cannot open ") + path + " for writing"), FIO_EINVAL);
+    PlanWriter w{f};
+    w.raw(kPlanMagic, sizeof kPlanMagic);
+    w.put<uint32_t>(kPlanVersion);
+    w.put<int32_t>(P->N);
+    w.put<int32_t>(P->phase.kind);
+    for (double v : P->phase.p)
+        w.put<double>(v);
+    w.put<double>(P->tol);
+    const fio_options &o = P->opt;
+    w.put<int32_t>(o.precision);
+    w.put<int32_t>(o.partition);
+    w.put<int32_t>(o.n_wedges);
+    w.put<int32_t>(P->factor_mode);
+    w.put<int32_t>(o.max_batch);
+    w.put<int32_t>(o.kernel_width);
+    w.put<int32_t>(o.r0);
+    w.put<int32_t>(o.verify_samples);
+    w.put<uint64_t>(o.seed);
+    w.put<double>(o.sep_tol_frac);
+    w.put<double>(o.nufft_tol_frac);
+    w.put<double>(o.sigma);
+    w.put<int32_t>(P->L);
+    w.put<int32_t>(P->w);
+    for (const WedgeHost &W : P->wedges) {
+        w.put<int32_t>((int32_t)W.members.size());
+        w.put<int32_t>(W.q);
+        w.put<int32_t>(W.qpad);
+        w.put<int32_t>(W.r);
+        w.put<int32_t>(W.attempts);
+        w.put<double>(W.sep_err);
+        w.vec(std::vector<int32_t>(W.C.begin(), W.C.end()));
+        w.vec(std::vector<int64_t>(W.R.begin(), W.R.end()));
+        w.vec(W.Z);
+        w.vec(W.P);
+    }
+    const uint64_t sum = w.h;
+    w.put<uint64_t>(sum);
+    const bool closed = std::fclose(f) == 0;
+    if (!w.ok || !closed)
+        return (set_error(std::string("write error on ") + path), FIO_EINVAL);
+    return FIO_OK;
+}
+
+fio_status load_plan(fio_plan_s *P, const char *path) {
+    using clock = std::chrono::steady_clock;
+    const auto t_start = clock::now();
+    FILE *f = std::fopen(path, "rb");
+    if (!f)
+        return (set_error(std::string("cannot open ") + path), FIO_EINVAL);
+    PlanReader r{f};
+    char magic[8] = {};
+    r.raw(magic, sizeof magic);
+    const uint32_t version = r.get<uint32_t>();
+    auto bad = [&](const std::string &why) {
+        std::fclose(f);
+        set_error(std::string(path) + ": " + why);
+        return FIO_EINVAL;
+    };
+    if (!r.ok || std::memcmp(magic, kPlanMagic, sizeof magic) != 0)
+        return bad("not a plan file");
+    if (version != kPlanVersion)
+        return bad("unsupported plan file version " + std::to_string(version));
+    const int N = r.get<int32_t>();
+    Phase ph{};
+    ph.kind = r.get<int32_t>();
+    for (double &v : ph.p)
+        v = r.get<double>();
+    const double tol = r.get<double>();
+    fio_options o;
+    fio_default_options(&o);
+    o.precision = r.get<int32_t>();
+    o.partition = r.get<int32_t>();
+    o.n_wedges = r.get<int32_t>();
+    const int mode = r.get<int32_t>();
+    o.max_batch = r.get<int32_t>();
+    o.kernel_width = r.get<int32_t>();
+    o.r0 = r.get<int32_t>();
+    o.verify_samples = r.get<int32_t>();
+    o.seed = r.get<uint64_t>();
+    o.sep_tol_frac = r.get<double>();
+    o.nufft_tol_frac = r.get<double>();
+    o.sigma = r.get<double>();
+    o.factor_mode = mode;
+    const int L = r.get<int32_t>(), w = r.get<int32_t>();
+    if (!r.ok)
+        return bad("truncated header");
+    if (N < 8 || (N & 1) || N > 4096 || ph.kind < 0 || ph.kind > 5 || !(tol >= 5e-7 && tol < 1) ||
+        (o.precision != FIO_F32 && o.precision != FIO_F64) ||
+        (o.partition != FIO_PART_EQUIANGULAR && o.partition != FIO_PART_CORONAE) ||
+        (mode != FIO_FACTORS_STORED && mode != FIO_FACTORS_REGEN) || o.max_batch < 1 || o.kernel_width < 0 ||
+        o.kernel_width > 16 || o.n_wedges < 0 || o.n_wedges > 4096 || o.sigma < 0 ||
+        (o.sigma > 0 && o.sigma < 1.25) || !(o.nufft_tol_frac > 0 && o.nufft_tol_frac <= 1) || L < 1 ||
+        L > (long long)N * N)
+        return bad("header out of range");
+    const int64_t NN = (int64_t)N * N;
+    std::vector<SavedWedge> saved((size_t)L);
+    for (SavedWedge &S : saved) {
+        S.members = r.get<int32_t>();
+        S.q = r.get<int32_t>();
+        S.qpad = r.get<int32_t>();
+        S.r = r.get<int32_t>();
+        S.attempts = r.get<int32_t>();
+        S.sep_err = r.get<double>();
+        if (!r.ok || S.members < 0 || S.members > NN || S.q < 0 || S.q > S.members || S.qpad != S.q + (S.q & 1))
+            return bad("wedge record out of range");
+        r.vec(S.C, S.members);
+        r.vec(S.R, NN);
+        r.vec(S.Z, (int64_t)S.C.size() * S.q);
+        r.vec(S.Pinv, (int64_t)S.q * (int64_t)S.R.size());
+        if (!r.ok)
+            return bad("truncated wedge record");
+        if (S.Z.size() != S.C.size() * (size_t)S.q || S.Pinv.size() != (size_t)S.q * S.R.size())
+            return bad("inconsistent factor sizes");
+        for (int32_t c : S.C)
+            if (c < 0 || c >= S.members)
+                return bad("column sample out of range");
+        for (int64_t x : S.R)
+            if (x < 0 || x >= NN)
+                return bad("row sample out of range");
+    }
+    const uint64_t expect = r.h;
+    const uint64_t sum = r.get<uint64_t>();
+    char extra;
+    const bool at_end = std::fread(&extra, 1, 1, f) == 0;
+    std::fclose(f);
+    if (!r.ok || sum != expect || !at_end)
+        return (set_error(std::string(path) + ": checksum mismatch or trailing bytes"), FIO_EINVAL);
+
+    P->N = N;
+    P->phase = ph;
+    P->tol = tol;
+    P->opt = o;
+    P->precision = o.precision;
+    FIO_HIP_TRY(hipGetDevice(&P->device));
+    fio_status st = plan_geometry(P);
+    if (st != FIO_OK)
+        return st;
+    if (P->L != L || P->w != w)
+        return (set_error(std::string(path) + ": wedge count or kernel width differs from this library's geometry"),
+                FIO_EINVAL);
+    for (int l = 0; l < L; ++l) {
+        WedgeHost &W = P->wedges[l];
+        SavedWedge &S = saved[(size_t)l];
+        if ((int)W.members.size() != S.members)
+            return (set_error(std::string(path) + ": wedge " + std::to_string(l) +
+                              " has another member count in this library's partition"),
+                    FIO_EINVAL);
+        W.q = S.q;
+        W.qpad = S.qpad;
+        W.r = S.r;
+        W.attempts = S.attempts;
+        W.sep_err = S.sep_err;
+        W.C.assign(S.C.begin(), S.C.end());
+        W.R.assign(S.R.begin(), S.R.end());
+        W.Z = std::move(S.Z);
+        W.P = std::move(S.Pinv);
+    }
+    P->regen = mode == FIO_FACTORS_REGEN;
+    if (P->regen) {
+        int qmax = 0;
+        for (const WedgeHost &W : P->wedges)
+            qmax = std::max(qmax, W.qpad);
+        if (qmax > kRegenMaxRank / (P->precision == FIO_F64 ? 2 : 1))
+            return (set_error("FIO_FACTORS_REGEN rank bound exceeded in the plan file"), FIO_ENOTSUP);
+    }
+    st = plan_layout(P);
+    if (st != FIO_OK)
+        return st;
+    P->factor_mode = mode;
+    double2 *d_xcoef = nullptr;
+    FIO_HIP_TRY(hipMalloc(&d_xcoef, NN * sizeof(double2)));
+    k_xcoef<<<(unsigned)((NN + 255) / 256), 256>>>(P->phase, N, d_xcoef);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        st = P->precision == FIO_F64 ? store_factors<double>(P, d_xcoef, true) : store_factors<float>(P, d_xcoef, true);
+    } else {
+        st = hip_fail(e, "k_xcoef");
+    }
+    (void)hipFree(d_xcoef);
+    if (st != FIO_OK)
+        return st;
+    FIO_HIP_TRY(apply_prepare(P));
+    FIO_HIP_TRY(hipDeviceSynchronize());
+    P->plan_ms = std::chrono::duration<double, std::milli>(clock::now() - t_start).count();
+    return FIO_OK;
 }
 
 fio_status build_plan(fio_plan_s *P) {

@@ -24,6 +24,8 @@ void es_parameters(double eps, double sigma, int forced_w, int &w, double &beta)
 double es_fourier(int w, double beta, double omega);
 zd host_residual(const Phase &ph, int N, long long p, double e1, double e2, double k1, double k2);
 fio_status build_plan(fio_plan_s *P);
+fio_status save_plan(const fio_plan_s *P, const char *path);
+fio_status load_plan(fio_plan_s *P, const char *path);
 void release_layout(fio_plan_s *P);
 std::vector<int> sample_members(int n, int k, uint64_t &state);
 fio_status gram_of_columns(const Phase &ph, int N, double2 *d_xcoef, double theta, const std::vector<double2> &cols,

@@ -94,6 +94,8 @@ def load_library():
         "fio_wedge_factors": (c_int, [P, c_int, c_int, P, P, c_int, P, P]),
         "fio_wedge_warp": (c_int, [P, c_int, c_int, P, P]),
         "fio_destroy": (c_int, [P]),
+        "fio_plan_save": (c_int, [P, c_char_p]),
+        "fio_plan_load": (c_int, [c_char_p, POINTER(P)]),
         "fio_profile": (c_int, [P, c_int]),
         "fio_profile_read": (c_int, [P, P, P]),
         "fio_learned_create": (c_int, [c_int, POINTER(fio_phase), c_int, c_ulonglong, POINTER(P)]),
@@ -199,6 +201,27 @@ class Plan:
                                ctypes.byref(h)))
         self.handle = h
         self.phase = ph
+
+    # -- plan files
+    def save(self, path):
+        """Write the plan (build inputs and compressed factors) to `path`: fio_plan_save."""
+        _check(self._lib.fio_plan_save(self.handle, str(path).encode()))
+
+    @classmethod
+    def load(cls, path):
+        """A plan written by save(), rebuilt on the current device: fio_plan_load."""
+        lib = load_library()
+        h = c_void_p()
+        _check(lib.fio_plan_load(str(path).encode(), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self._lib = lib
+        self.handle = h
+        self._learned = None
+        self.phase = None
+        info = self.info()
+        self.N = int(info["N"])
+        self.precision = "f64" if info["precision"] == PRECISIONS["f64"] else "f32"
+        return self
 
     # -- lifetime
     def close(self):

@@ -127,3 +127,22 @@ def test_python_binding_raises_without_device_tensor():
     with pytest.raises(fio.FioError) as e:
         fio.Plan(63, "c1c2", 1e-4, params=(1.0,))
     assert e.value.status == fio.FIO_EINVAL
+
+
+def test_plan_files_are_checked_before_device_use(lib, tmp_path):
+    """fio_plan_save / fio_plan_load reject null arguments, missing files and
+    files that are not (whole) plan files before any device call."""
+    h = ctypes.c_void_p()
+    assert lib.fio_plan_save(None, b"/tmp/x") == fio.FIO_EINVAL
+    assert lib.fio_plan_load(None, ctypes.byref(h)) == fio.FIO_EINVAL
+    assert lib.fio_plan_load(str(tmp_path / "none.plan").encode(), ctypes.byref(h)) == fio.FIO_EINVAL
+    assert not h.value
+    junk = tmp_path / "junk.plan"
+    junk.write_bytes(b"not a plan at all, just bytes" * 4)
+    assert lib.fio_plan_load(str(junk).encode(), ctypes.byref(h)) == fio.FIO_EINVAL
+    assert b"not a plan file" in lib.fio_last_error()
+    # the right magic and version, then a header cut short
+    cut = tmp_path / "cut.plan"
+    cut.write_bytes(b"FIOPLAN1" + (1).to_bytes(4, "little") + (128).to_bytes(4, "little"))
+    assert lib.fio_plan_load(str(cut).encode(), ctypes.byref(h)) == fio.FIO_EINVAL
+    assert not h.value
