@@ -233,7 +233,7 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
     const int z0 = pruned ? 2 * (B1 - B1 / 2) : B1 - B1 / 2, z1 = pruned ? n - 2 * (B1 / 2) : n - B1 / 2;
     for (int i = z0 * nb + tid; i < z1 * nb; i += nt)
         buf[i] = cmake<T>(0, 0);
-    const FastDiv &fnb = it.fnb, &fq = W.fq, &fb1 = W.fB1, &fn = W.fn1;
+    const FastDiv &fnb = it.fnb, &fq = W.fq, &fb1 = W.fB1;
     const cplx<T> *H = a.H + (long long)b * a.H_stride + W.H_off;
     cplx<T> *G = a.G + (long long)b * a.G_stride + W.G_off;
     // H is plane-major (plane P = tau / CPU, element [(P * B1 + k1) * CPU + tau % CPU]): an item of

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_direct_probe(Phase ph, int N, const cpl
     si[threadIdx.x] = ai;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
+        if ((int)threadIdx.x < o) {
             sr[threadIdx.x] += sr[threadIdx.x + o];
             si[threadIdx.x] += si[threadIdx.x + o];
         }

@@ -165,7 +165,7 @@ __global__ void k_colsum(const float *__restrict__ X, int n, int N, float *__res
     red[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o)
+        if ((int)threadIdx.x < o)
             red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
@@ -189,7 +189,7 @@ __global__ void k_mse(const float *__restrict__ Y, const float *__restrict__ T, 
     red[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (threadIdx.x < o)
+        if ((int)threadIdx.x < o)
             red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
