@@ -403,8 +403,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the wedge sharding is described "
-              "in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the apply would shard by wedge, "
+              "with one sum of the partial outputs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     {"batched": run_batched, "batch512": run_batch512, "uneven": run_uneven,
      "learned": run_learned}[args.workload](args)

@@ -9,7 +9,8 @@ arithmetic.
 
 Contents:
   * direct.c / direct.py -- plain FP64 direct summation of eq. (dfio),
-    OpenMP over output points (the definition oracle, the judge);
+    OpenMP over output points (the definition itself, against which every
+    parity test compares);
   * reference.py -- NumPy FP64: phase families, the dense operator matrix
     for tiny N, the wedge partition of Section 1.3, the residual phase,
     the randomized separation of Section 3.2, a step-by-step model of the
