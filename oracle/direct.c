@@ -25,9 +25,11 @@
  * h is FP64; the total phase is reduced by its nearest integer before
  * sin/cos(2 pi r); accumulation is FP64, summed per frequency row first.
  *
- * ORACLE_PLANT (tests only): compiling with -DORACLE_PLANT=1/2/3 plants a
- * known mistake (flipped sign of h / dropped 1/N / swapped x1, x2 in h) so
- * that a test can show the pins catch it.  The default build plants nothing.
+ * ORACLE_PLANT (tests only): compiling with -DORACLE_PLANT=1..6 plants a
+ * known mistake (flipped sign of h / dropped 1/N / swapped x1, x2 in h /
+ * sin and cos exchanged in c1, c2 / 2 pi for 4 pi in r1, r2 / the adjoint
+ * without the conjugation) so that a test can show the pins catch it.  The
+ * default build plants nothing.
  */
 #include <math.h>
 #include <stdint.h>
@@ -47,8 +49,13 @@ static double oracle_h(int kind, const double *p, double x1, double x2, double k
     case 1:
         return p[0] * sqrt(k1 * k1 + k2 * k2);
     case 2: {
+#if defined(ORACLE_PLANT) && ORACLE_PLANT == 4
+        double c1 = (2.0 + cos(TWO_PI * x1) * cos(TWO_PI * x2)) / 16.0;
+        double c2 = (2.0 + sin(TWO_PI * x1) * sin(TWO_PI * x2)) / 16.0;
+#else
         double c1 = (2.0 + sin(TWO_PI * x1) * sin(TWO_PI * x2)) / 16.0;
         double c2 = (2.0 + cos(TWO_PI * x1) * cos(TWO_PI * x2)) / 16.0;
+#endif
         return p[0] * sqrt(c1 * c1 * k1 * k1 + c2 * c2 * k2 * k2);
     }
     case 3: {
@@ -56,8 +63,13 @@ static double oracle_h(int kind, const double *p, double x1, double x2, double k
         return rho * sqrt(k1 * k1 + k2 * k2);
     }
     case 4: {
+#if defined(ORACLE_PLANT) && ORACLE_PLANT == 5
+        double r1 = (2.0 + sin(TWO_PI * x1)) * (2.0 + sin(TWO_PI * x2)) / 9.0;
+        double r2 = (2.0 + cos(TWO_PI * x1)) * (2.0 + cos(TWO_PI * x2)) / 9.0;
+#else
         double r1 = (2.0 + sin(2.0 * TWO_PI * x1)) * (2.0 + sin(2.0 * TWO_PI * x2)) / 9.0;
         double r2 = (2.0 + cos(2.0 * TWO_PI * x1)) * (2.0 + cos(2.0 * TWO_PI * x2)) / 9.0;
+#endif
         return p[0] * sqrt(r1 * r1 * k1 * k1 + r2 * r2 * k2 * k2);
     }
     case 5: {
@@ -148,6 +160,75 @@ int oracle_direct(int N, int kind, const double *p, int ns, const int64_t *xidx,
         for (int b = 0; b < nrhs; ++b) {
             u[2 * ((int64_t)s * nrhs + b)] = acc_re[b] * scale;
             u[2 * ((int64_t)s * nrhs + b) + 1] = acc_im[b] * scale;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Adjoint (Section 3.5): the Fourier coefficients of L*g,
+ *
+ *   hhat[s*nrhs + b] = (1/N) sum_{y in X} exp(-2 pi i Phi(y, xi_s)) g_b(y),
+ *
+ * the conjugate transpose of the operator above as a map from fhat on Omega
+ * to u on X.
+ *   xiidx : ns flat centred frequency indices (k1 + N/2)*N + (k2 + N/2)
+ *   g     : nrhs arrays of N*N complex (interleaved), row-major n1*N + n2
+ *   hhat  : ns*nrhs complex (interleaved) output
+ * Same arithmetic as oracle_direct: y.xi mod 1 in integers, h in FP64,
+ * reduction by the nearest integer, FP64 accumulation summed per row of y.
+ * Returns 0, or -1 on bad arguments.
+ */
+int oracle_direct_adjoint(int N, int kind, const double *p, int ns, const int64_t *xiidx, int nrhs,
+                          const double *g, double *hhat, int nthreads)
+{
+    if (N <= 0 || (N & 1) || ns < 0 || nrhs <= 0 || nrhs > 64)
+        return -1;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    const int h = N / 2;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int s = 0; s < ns; ++s) {
+        const int64_t k1 = xiidx[s] / N - h, k2 = xiidx[s] % N - h;
+        double acc_re[64], acc_im[64];
+        for (int b = 0; b < nrhs; ++b)
+            acc_re[b] = acc_im[b] = 0.0;
+        for (int n1 = 0; n1 < N; ++n1) {
+            double row_re[64], row_im[64];
+            for (int b = 0; b < nrhs; ++b)
+                row_re[b] = row_im[b] = 0.0;
+            const double x1 = (double)n1 / N;
+            for (int n2 = 0; n2 < N; ++n2) {
+                const double x2 = (double)n2 / N;
+                int64_t ip = ((int64_t)n1 * k1 + (int64_t)n2 * k2) % N;
+                if (ip < 0)
+                    ip += N;
+                double ph = (double)ip / N + oracle_h(kind, p, x1, x2, (double)k1, (double)k2);
+#if defined(ORACLE_PLANT) && ORACLE_PLANT == 6
+                ph = -ph;
+#endif
+                double r = ph - rint(ph);
+                /* exp(-2 pi i r) */
+                double c = cos(TWO_PI * r), sn = -sin(TWO_PI * r);
+                const int64_t cell = (int64_t)n1 * N + n2;
+                for (int b = 0; b < nrhs; ++b) {
+                    const double *v = g + 2 * ((int64_t)b * N * N + cell);
+                    row_re[b] += c * v[0] - sn * v[1];
+                    row_im[b] += c * v[1] + sn * v[0];
+                }
+            }
+            for (int b = 0; b < nrhs; ++b) {
+                acc_re[b] += row_re[b];
+                acc_im[b] += row_im[b];
+            }
+        }
+        for (int b = 0; b < nrhs; ++b) {
+            hhat[2 * ((int64_t)s * nrhs + b)] = acc_re[b] / N;
+            hhat[2 * ((int64_t)s * nrhs + b) + 1] = acc_im[b] / N;
         }
     }
     return 0;

@@ -49,6 +49,10 @@ def _load(path: str | None = None):
         lib.oracle_direct.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_direct_adjoint.restype = ctypes.c_int
+        lib.oracle_direct_adjoint.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         lib.oracle_h_batch.restype = None
         lib.oracle_h_batch.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 5
         lib.oracle_max_threads.restype = ctypes.c_int
@@ -104,6 +108,35 @@ def direct(N: int, kind: int, params, fhat, xidx, member=None, only: int = 0, th
                                part.ctypes.data, int(threads))
         if rc != 0:
             raise ValueError("oracle_direct rejected its arguments")
+        out[:, b0:b0 + nb] = part
+    out = out.T
+    return out[0] if single else out
+
+
+def direct_adjoint(N: int, kind: int, params, g, xiidx, threads: int = 0, lib_path: str | None = None) -> np.ndarray:
+    """Fourier coefficients of L*g at flat centred frequency indices `xiidx`
+    by FP64 direct summation (Section 3.5):
+    hhat(xi) = (1/N) sum_y exp(-2 pi i Phi(y, xi)) g(y).
+
+    g: (N, N) or (B, N, N) complex, row-major spatial layout.  Returns (ns,)
+    or (B, ns) complex128.
+    """
+    ga = np.asarray(g)
+    single = ga.ndim == 2
+    ga = np.ascontiguousarray(ga.reshape(-1, N, N).astype(np.complex128))
+    B = ga.shape[0]
+    ks = np.ascontiguousarray(np.asarray(xiidx, dtype=np.int64).ravel())
+    out = np.empty((ks.size, B), dtype=np.complex128)
+    p = _params(params)
+    lib = _load(lib_path)
+    for b0 in range(0, B, 64):
+        nb = min(64, B - b0)
+        part = np.empty((ks.size, nb), dtype=np.complex128)
+        chunk = np.ascontiguousarray(ga[b0:b0 + nb])
+        rc = lib.oracle_direct_adjoint(int(N), int(kind), p.ctypes.data, ks.size, ks.ctypes.data, nb,
+                                       chunk.ctypes.data, part.ctypes.data, int(threads))
+        if rc != 0:
+            raise ValueError("oracle_direct_adjoint rejected its arguments")
         out[:, b0:b0 + nb] = part
     out = out.T
     return out[0] if single else out

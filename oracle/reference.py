@@ -160,6 +160,22 @@ def direct(N, kind, p, fhat, xidx, member=None, only=0, chunk=64):
     return out
 
 
+def direct_adjoint(N, kind, p, g, xiidx, chunk=64):
+    """Fourier coefficients of L*g at flat centred indices `xiidx` (Section 3.5):
+    hhat(xi) = (1/N) sum_y exp(-2 pi i Phi(y, xi)) g(y), vectorised NumPy."""
+    gv = np.asarray(g, dtype=np.complex128).reshape(N * N)
+    x1, x2 = grid_x(N)
+    xiidx = np.asarray(xiidx, dtype=np.int64)
+    k1 = xiidx // N - N // 2
+    k2 = xiidx % N - N // 2
+    out = np.empty(xiidx.size, dtype=np.complex128)
+    for s in range(0, xiidx.size, chunk):
+        a1 = k1[s:s + chunk, None].astype(float)
+        a2 = k2[s:s + chunk, None].astype(float)
+        out[s:s + chunk] = np.conj(_expi(phase(kind, p, x1[None, :], x2[None, :], a1, a2))) @ gv / N
+    return out
+
+
 def multiplier_solution(N, hfun, f):
     """Closed form for Phi = x.xi + h(xi) (x-independent h): u = IDFT(e^{2 pi i h(xi)} DFT f).
 

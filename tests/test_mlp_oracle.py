@@ -75,3 +75,59 @@ def test_feature_map_is_periodic():
     b = mlp.features(x1 + 1, x2 - 2, 0.3 + 2 * math.pi, 1.2)
     np.testing.assert_allclose(a, b, atol=1e-12)
     assert a.shape == (50, 16)
+
+
+def test_adam_first_step_and_constant_gradient_closed_forms():
+    """Bias-corrected Adam: with a constant gradient g every step moves each
+    parameter by exactly lr * g / (|g| + eps), whatever the scale of g, since
+    the corrected moments are then g and g^2 at every t."""
+    rng = np.random.default_rng(3)
+    dims = (4, 3, 3, 3, 2)
+    params = mlp.init_params(rng, dims)
+    g = mlp.init_params(rng, dims)
+    g = [(gW * 10.0 ** rng.integers(-3, 3), gb + 0.5) for gW, gb in g]
+    state = {}
+    lr, eps = 1e-2, 1e-8
+    cur = params
+    for t in range(1, 6):
+        nxt = mlp.adam_step(cur, g, state, lr, eps=eps)
+        for (W0, b0), (W1, b1), (gW, gb) in zip(cur, nxt, g):
+            np.testing.assert_allclose(W0 - W1, lr * gW / (np.abs(gW) + eps), rtol=1e-9, atol=1e-15)
+            np.testing.assert_allclose(b0 - b1, lr * gb / (np.abs(gb) + eps), rtol=1e-9, atol=1e-15)
+        cur = nxt
+    assert state["t"] == 5
+
+
+def test_adam_second_step_by_hand():
+    """Two scalar steps worked out by hand: g1 = 1, g2 = -3, b1 = 0.9, b2 = 0.999.
+    t = 1: m = 0.1, v = 0.001, corrected 1 and 1 -> step lr.
+    t = 2: m = 0.09 - 0.3 = -0.21, v = 0.000999 + 0.009 = 0.009999;
+           corrected m = -0.21/0.19, v = 0.009999/0.001999 -> step lr (-0.21/0.19)/sqrt(0.009999/0.001999)."""
+    p = [(np.array([[2.0]]), np.array([0.0]))]
+    state = {}
+    lr = 0.1
+    p1 = mlp.adam_step(p, [(np.array([[1.0]]), np.array([1.0]))], state, lr, eps=0.0)
+    assert abs(p1[0][0][0, 0] - (2.0 - lr)) < 1e-15
+    p2 = mlp.adam_step(p1, [(np.array([[-3.0]]), np.array([-3.0]))], state, lr, eps=0.0)
+    step = lr * (-0.21 / 0.19) / math.sqrt(0.009999 / 0.001999)
+    assert abs(p2[0][0][0, 0] - (2.0 - lr - step)) < 1e-14
+    assert abs(p2[0][1][0] - (0.0 - lr - step)) < 1e-14
+
+
+def test_factor_targets_equal_left_singular_vectors_times_singular_values():
+    """alpha* = A(:, C) V / s1 is U S / s1 of the SVD A(:, C) = U S V^H: the
+    columns are orthogonal, the first has unit norm, and their norms are the
+    singular values over s1 (an independent construction through numpy's SVD)."""
+    rng = np.random.default_rng(4)
+    n, r = 300, 24
+    A = rng.standard_normal((n, 5)) @ rng.standard_normal((5, r)) + 1j * rng.standard_normal((n, r)) * 0.1
+    U, S, Vh = np.linalg.svd(A, full_matrices=False)
+    V = Vh.conj().T[:, :16]
+    out = mlp.factor_targets(A, V, S[0])
+    al = out[:, 0::2] + 1j * out[:, 1::2]
+    np.testing.assert_allclose(al, U[:, :16] * (S[:16] / S[0]), atol=1e-12)
+    G = al.conj().T @ al
+    np.testing.assert_allclose(np.abs(G - np.diag(np.diag(G))), 0, atol=1e-12)
+    assert abs(np.linalg.norm(al[:, 0]) - 1.0) < 1e-12
+    # interleaving: real part at even columns, imaginary part at odd ones
+    assert np.array_equal(out[:, 0], al[:, 0].real) and np.array_equal(out[:, 1], al[:, 0].imag)
