@@ -28,8 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
-FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x FMA (2 flop) x 2.4 GHz, non-packed FP32
+HBM_PEAK_GBS = 8000.0             # MI355X HBM3E, published
+FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector, published (counts packed FP32 FMAs)
+FP32_NONPACKED_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x FMA (2 flop) x 2.4 GHz: the rate without
+                                  # packed FP32, which this build disables
 STAGES = ("window_rowfft", "colfft", "interp_combine")
 
 
@@ -43,13 +45,16 @@ def log(msg):
 def stage_work(plan, B):
     """Algorithmic bytes and flops per stage for one apply of B right-hand sides.
 
-    Per wedge (box B1 x B2, grid n1 x n2, rank q padded to even, |W| members),
-    complex64 = 8 bytes:
+    Per wedge (box B1 x B2, grid n1 x n2, rank q, |W| members), complex64 =
+    8 bytes; bytes count the rank padded to even (the stored 16-byte rank
+    pairs the kernels must move), flops the true rank:
       stage 0 reads fhat on W and gamma^xi (q per member), writes B1 * n2 * q;
       stage 1 reads B1 * n2 * q, writes n1 * n2 * q;
       stage 2 reads n1 * n2 * q and gamma^x (N^2 q, once per launch of up to 8
               right-hand sides), writes N^2 per right-hand side; its flops are
-              N^2 (4 w^2 q + 8 q + 8) per wedge and right-hand side.
+              N^2 q (4 w^2 + 4 w + 8) per wedge and right-hand side (a w x w
+              real-weighted stencil of complex values, the w-point weights of
+              both axes, and the factor and modulation products).
     """
     info = plan.info()
     N, w = info["N"], info["kernel_width"]
@@ -70,13 +75,35 @@ def stage_work(plan, B):
         by[1] += es * (B1 * n2 * q + n1 * n2 * q) * B
         by[2] += es * (n1 * n2 * q) * B
         gx_bytes += es * NN * q
-        fl += NN * (4.0 * w * w * q + 8.0 * q + 8.0) * B
+        fl += NN * wi["rank"] * (4.0 * w * w + 4.0 * w + 8.0) * B
     by[2] += gx_bytes * math.ceil(B / 8) + es * NN * B
     return by, fl
 
 
-def cpu_baseline(N, phase_kind, params, fh, samples, seed):
-    """Time the FP64 direct-sum oracle on a bounded sample of outputs (all host threads)."""
+def cpu_model():
+    """Host CPU model name (lscpu's "Model name", else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True,
+                             timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def oracle_check(N, phase_kind, params, fh, samples, seed):
+    """FP64 direct-sum oracle at `samples` random outputs of every right-hand
+    side (all host threads); returns (sample indices, reference values, seconds, threads)."""
     import numpy as np
     from oracle import direct as od
 
@@ -85,13 +112,30 @@ def cpu_baseline(N, phase_kind, params, fh, samples, seed):
     xs = np.sort(rng.choice(N * N, size=samples, replace=False))
     t0 = time.perf_counter()
     ref = od.direct(N, phase_kind, params, fh, xs)
-    dt = time.perf_counter() - t0
+    return xs, ref, time.perf_counter() - t0, od.max_threads()
+
+
+def cpu_baseline(N, phase_kind, params, fh, samples, dt, threads, one_thread_samples):
+    """The oracle's throughput, extrapolated to all N^2 outputs, from the timed
+    all-thread check and from a smaller run on one thread."""
+    import numpy as np
+    from oracle import direct as od
+
     B = fh.shape[0]
-    full_s = dt * (N * N) / samples
-    return dict(value=B / full_s, unit="applies/s", cores=od.max_threads(), kind="oracle",
+    rng = np.random.default_rng(99)
+    xs1 = np.sort(rng.choice(N * N, size=one_thread_samples, replace=False))
+    t0 = time.perf_counter()
+    od.direct(N, phase_kind, params, fh, xs1, threads=1)
+    dt1 = time.perf_counter() - t0
+    od.direct(N, phase_kind, params, fh[:1], xs1[:1], threads=threads)  # restore the thread count
+    return dict(value=B / (dt * (N * N) / samples), unit="applies/s", cores=threads, kind="oracle",
+                model=cpu_model(),
                 sample="%d random outputs x %d RHS of the N=%d workload (%.2e kernel terms, shared by the RHS) "
-                       "in %.1f s; extrapolated to all N^2 outputs" % (samples, B, N, float(samples) * N * N, dt)), \
-        xs, ref
+                       "in %.1f s on %d threads; extrapolated to all N^2 outputs"
+                       % (samples, B, N, float(samples) * N * N, dt, threads),
+                one_thread=dict(value=B / (dt1 * (N * N) / one_thread_samples), unit="applies/s", cores=1,
+                                sample="%d random outputs x %d RHS in %.1f s on one thread"
+                                       % (one_thread_samples, B, dt1)))
 
 
 def tuned_plan(N, tol, B, fixed=None, factor_mode="auto"):
@@ -199,8 +243,11 @@ def run_batched(args):
     alg_bytes = by[dom] / lps[dom]
     if dom == 2:
         achieved = fl / lps[2] / (per_launch_ms[2] * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=achieved, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / FP32_VALU_PEAK_TFLOPS, traffic=traffic, kernel=kname)
+        roof = dict(bound="alu", achieved=achieved, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=achieved / FP32_PEAK_TFLOPS, traffic=traffic, kernel=kname,
+                    peak_nonpacked=FP32_NONPACKED_TFLOPS, frac_nonpacked=achieved / FP32_NONPACKED_TFLOPS,
+                    flops_per_launch=fl / lps[2],
+                    flops_formula="sum over wedges of N^2 q (4 w^2 + 4 w + 8) per right-hand side, true rank q")
     else:
         achieved = alg_bytes / (per_launch_ms[dom] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
@@ -211,9 +258,13 @@ def run_batched(args):
     stages = {}
     for i, name in enumerate(STAGES):
         bpl = by[i] / max(1e-9, lps[i])
+        gbs = bpl / (per_launch_ms[i] * 1e-3) / 1e9 if per_launch_ms[i] > 0 else None
         stages[name] = dict(ms_per_step=stage_ms[i], ms_per_launch=per_launch_ms[i], launches_per_step=lps[i],
-                            gbs=bpl / (per_launch_ms[i] * 1e-3) / 1e9 if per_launch_ms[i] > 0 else None)
+                            algorithmic_bytes_per_launch=bpl, gbs=gbs,
+                            hbm_frac=gbs / HBM_PEAK_GBS if gbs else None,
+                            hbm_frac_of_copy=gbs / copy_gbs if gbs else None)
     stages["interp_combine"]["tflops"] = fl / (stage_ms[2] * 1e-3) / 1e12
+    stages["interp_combine"]["fp32_frac"] = stages["interp_combine"]["tflops"] / FP32_PEAK_TFLOPS
     res = dict(metric="FIO applies/s at N=1024, rel-l2<=1e-4", value=value, unit="applies/s", n_gpus=1,
                steps=steps, warmup=args.warmup, ms_per_step=1e3 * elapsed / steps, higher_is_better=True,
                scaling="weak", vs_baseline=None, dtype="c64 (fp32 data, fp64 phase and points)", data="synthetic",
@@ -228,15 +279,27 @@ def run_batched(args):
                            parallelism="single GPU"),
                roofline=roof, stages=stages,
                comparison=dict(per_rhs_loop_applies_per_s=single_value, batched_applies_per_s=value))
-    if not args.no_cpu_baseline:
-        log("CPU oracle baseline on %d sampled outputs" % args.cpu_samples)
-        cb, xs, refv = cpu_baseline(N, 2, (1.0,), fh, args.cpu_samples, seed=4321)
-        got = out.cpu().numpy().reshape(B, N * N)[:, xs].astype(np.complex128)
-        res["rel_l2_vs_oracle"] = float(np.linalg.norm(got - refv) / np.linalg.norm(refv))
-        res["cpu_baseline"] = cb
-    else:
+    # accuracy gate: every right-hand side against the FP64 oracle
+    log("oracle check on %d sampled outputs x %d RHS" % (args.cpu_samples, B))
+    xs, refv, dt, threads = oracle_check(N, 2, (1.0,), fh, args.cpu_samples, seed=4321)
+    got = out.cpu().numpy().reshape(B, N * N)[:, xs].astype(np.complex128)
+    errs = [float(np.linalg.norm(got[b] - refv[b]) / np.linalg.norm(refv[b])) for b in range(B)]
+    res["rel_l2_vs_oracle"] = max(errs)
+    res["rel_l2_vs_oracle_per_rhs"] = errs
+    res["oracle_samples"] = int(args.cpu_samples)
+    if args.no_cpu_baseline:
         res["cpu_baseline"] = None
+    else:
+        log("CPU oracle baseline: one thread on %d outputs" % args.cpu_one_thread_samples)
+        res["cpu_baseline"] = cpu_baseline(N, 2, (1.0,), fh, args.cpu_samples, dt, threads,
+                                           args.cpu_one_thread_samples)
+    bad = max(errs) > args.tol
+    if bad:
+        res["invalid"] = "relative l2 error %.3e above the budget %.1e" % (max(errs), args.tol)
+        res["value"] = None
     print(json.dumps(res), flush=True)
+    if bad:
+        sys.exit(3)
 
 
 def run_batch512(args):
@@ -389,6 +452,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--cpu-samples", type=int, default=3072)
+    ap.add_argument("--cpu-one-thread-samples", type=int, default=160)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the per-RHS loop comparison")
     ap.add_argument("--factor-mode", choices=("auto", "stored", "regen"), default="auto",

@@ -176,7 +176,9 @@ fio_status fio_apply_batch(fio_plan_t plan, int B, const void *fhat, void *u, vo
  * in one launch of each stage; the launch sequence is captured into a HIP
  * graph that is replayed while the plans and batch sizes stay the same (new
  * pointers refresh its argument table).  Instances run one after another
- * instead when their kernel widths differ or B[i] exceeds plan i's max_batch. */
+ * instead when their kernel widths differ, B[i] exceeds plan i's max_batch,
+ * or a plan appears more than once in the list (its one workspace cannot
+ * hold two instances at once). */
 fio_status fio_apply_multi(int n, const fio_plan_t *plans, const void *const *fhat, void *const *u,
                            const int *B, void *stream);
 
@@ -289,6 +291,25 @@ fio_status fio_learned_forward(fio_learned_t m, int n, const float *feat, float 
  * flat gradients in the parameter order (no update) and the loss. */
 fio_status fio_learned_grads(fio_learned_t m, int n, const float *feat, const float *target, float *grads,
                              double *loss);
+/* Introspection of the training targets (for checks against a CPU model).
+ * fio_learned_basis: host copy of wedge ell's column sample C (cols[2c],
+ * cols[2c+1] = centred frequency (k1, k2) of column c), of the joint right
+ * singular vectors V (r x 16 complex, row-major, interleaved) and of s1, the
+ * leading joint singular value per scale (sqrt of the Gram matrix's largest
+ * eigenvalue over the scale count); *r = column count.  cap is the capacity
+ * of cols (2 cap doubles) and V (32 cap doubles); FIO_EINVAL if r > cap or
+ * no data was generated.
+ * fio_learned_targets: the targets alpha*_s(x) = A_s(x, C) V sqrt(N^2) / s1
+ * (the residual kernel exp(2 pi i Phi_ell) of Section 3.2 at scale s) at nx
+ * given flat grid indices, out[i*32 + 2t], out[i*32 + 2t + 1] = re, im of
+ * factor t, computed by the kernel that generates the training data. */
+fio_status fio_learned_basis(fio_learned_t m, int ell, int cap, int *r, double *cols, double *V, double *s1);
+fio_status fio_learned_targets(fio_learned_t m, int ell, double scale, int nx, const long long *xidx, float *out);
+/* One Adam update (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step
+ * count kept by the network and reset by fio_learned_params) of the FP32
+ * parameters with the given flat gradients (host, parameter order), by the
+ * kernel the training loop uses. */
+fio_status fio_learned_adam_step(fio_learned_t m, const float *grads, double lr);
 fio_status fio_learned_save(fio_learned_t m, const char *path);
 fio_status fio_learned_load(const char *path, fio_learned_t *out);
 fio_status fio_learned_destroy(fio_learned_t m);

@@ -7,6 +7,7 @@ g++.  Objects are built in parallel and linked with hipcc.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import shutil
 import subprocess
@@ -37,14 +38,28 @@ def _run(cmd):
     return p.stdout
 
 
+def source_digest() -> str:
+    """SHA-256 (first 16 hex digits) of every file under csrc/: the build id
+    that fio_version() reports and the autotuner keys its cache with."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        path = os.path.join(CSRC, name)
+        if os.path.isfile(path):
+            h.update(name.encode())
+            with open(path, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(jobs: int | None = None, verbose: bool = False) -> str:
     """Compile every source (always) and link libfio.so; returns its path."""
     os.makedirs(OBJ_DIR, exist_ok=True)
     cmds = []
     objs = []
+    build_id = ["-DFIO_BUILD_ID=\"%s\"" % source_digest()]
     for src in HIP_SOURCES:
         obj = os.path.join(OBJ_DIR, src + ".o")
-        cmds.append([HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([HIPCC] + HIP_FLAGS + build_id + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     for src in CXX_SOURCES:
         obj = os.path.join(OBJ_DIR, src + ".o")

@@ -105,7 +105,10 @@ void fio_default_options(fio_options *o) {
 
 const char *fio_last_error(void) { return get_error(); }
 
-const char *fio_version(void) { return "fio-mi355x 0.1 (gfx950)"; }
+#ifndef FIO_BUILD_ID
+#define FIO_BUILD_ID "unstamped"
+#endif
+const char *fio_version(void) { return "fio-mi355x 0.2 (gfx950, sources " FIO_BUILD_ID ")"; }
 
 fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, double tol, const fio_options *opt,
                        fio_plan_t *out) {

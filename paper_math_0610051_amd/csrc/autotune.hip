@@ -138,10 +138,14 @@ fio_status probe_error(fio_plan_s *P, const void *fhat, const void *u, int ns, u
                                    : probe_t<float>(P, fhat, u, ns, seed, err, s);
 }
 
-static std::string tune_key(int N, const fio_phase *ph, double tol, int precision, int B) {
+// Cache key: everything a choice depends on, including the library build
+// (a cached choice of an older kernel build is not reused).
+static std::string tune_key(int N, const fio_phase *ph, double tol, const fio_options &o, int B) {
     char buf[512];
-    std::snprintf(buf, sizeof(buf), "N=%d kind=%d p=%.9g,%.9g,%.9g tol=%.3g prec=%d B=%d", N, ph->kind, ph->p[0],
-                  ph->p[1], ph->p[2], tol, precision, B);
+    std::snprintf(buf, sizeof(buf),
+                  "N=%d kind=%d p=%.9g,%.9g,%.9g tol=%.3g prec=%d part=%d mode=%d seed=%llu B=%d build=%s", N,
+                  ph->kind, ph->p[0], ph->p[1], ph->p[2], tol, o.precision, o.partition, o.factor_mode, o.seed, B,
+                  fio_version());
     return buf;
 }
 
@@ -229,7 +233,7 @@ fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp,
     else
         fio_default_options(&o);
     const char *cache = std::getenv("FIO_TUNE_CACHE");
-    const std::string key = tune_key(N, phase, tol, o.precision, B);
+    const std::string key = tune_key(N, phase, tol, o, B);
     if (ntried)
         *ntried = 0;
     if (cache_lookup(cache, key, best))
@@ -277,10 +281,13 @@ fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp,
             ws.push_back(lower);
         return ws;
     };
+    bool failed = false;  // a failed launch or probe ends the whole search
     for (double sg : sigmas)
         for (const auto &sp : splits)
             for (int kw : widths(tol * sp[1], sg))
             for (int L : Ls) {
+                if (failed)
+                    break;
                 fio_options c = o;
                 c.n_wedges = L;
                 c.sigma = sg;
@@ -313,6 +320,7 @@ fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp,
                 if (ae != hipSuccess) {
                     fio_destroy(P);
                     result = hip_fail(ae, "fio_autotune apply");
+                    failed = true;
                     break;
                 }
                 r.ms_per_rhs = ms / (3.0 * B);
@@ -321,6 +329,7 @@ fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp,
                 fio_destroy(P);
                 if (st != FIO_OK) {
                     result = st;
+                    failed = true;
                     break;
                 }
                 r.error = err;

@@ -236,15 +236,17 @@ __global__ void k_gather_batch(const unsigned short *__restrict__ feat, const fl
 }
 
 // Training samples of one (scale, wedge) group: features and alpha* targets
-// at nx grid points drawn from the group's counter-based stream.
+// at nx grid points drawn from the group's counter-based stream, or at the
+// given flat grid indices xlist when it is not null (feat may then be null).
 __global__ void k_make_samples(Phase ph, int N, double theta, double s, const double2 *__restrict__ cols, int r,
                                const double2 *__restrict__ V, double inv_s1, unsigned long long key, int nx,
-                               unsigned short *__restrict__ feat, float *__restrict__ target) {
+                               const long long *__restrict__ xlist, unsigned short *__restrict__ feat,
+                               float *__restrict__ target) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nx)
         return;
     const long long NN = (long long)N * N;
-    const long long p = (long long)(splitmix64(key + (unsigned long long)i) % (unsigned long long)NN);
+    const long long p = xlist ? xlist[i] : (long long)(splitmix64(key + (unsigned long long)i) % (unsigned long long)NN);
     const double x1 = (double)(p / N) / N, x2 = (double)(p % N) / N;
     const XCoef c = phase_xcoef(ph, x1, x2);
     double g1, g2;
@@ -264,11 +266,13 @@ __global__ void k_make_samples(Phase ph, int N, double theta, double s, const do
             ai[t] += cs * v.y + sn * v.x;
         }
     }
-    float f[kNetIn];
-    net_features(x1, x2, theta, s, f);
+    if (feat) {
+        float f[kNetIn];
+        net_features(x1, x2, theta, s, f);
 #pragma unroll
-    for (int k = 0; k < kNetIn; ++k)
-        feat[(long long)i * kNetIn + k] = f2bf(f[k]);
+        for (int k = 0; k < kNetIn; ++k)
+            feat[(long long)i * kNetIn + k] = f2bf(f[k]);
+    }
 #pragma unroll
     for (int t = 0; t < kNetRank; ++t) {
         target[(long long)i * kNetOut + 2 * t] = (float)(ar[t] * inv_s1);
@@ -592,6 +596,8 @@ fio_status fio_learned_generate(fio_learned_t m, int nscales, const double *scal
     FIO_HIP_TRY(hipMalloc(&m->d_target, sizeof(float) * total * kNetOut));
     m->nsamples = total;
     m->cols.assign(L, {});
+    m->colk.assign(L, {});
+    m->theta = thetas;
     m->V.assign(L, {});
     m->s1.assign(L, 1.0);
     double2 *d_xcoef = nullptr, *d_cols = nullptr, *d_V = nullptr;
@@ -618,9 +624,12 @@ fio_status fio_learned_generate(fio_learned_t m, int nscales, const double *scal
         const int r = std::min(r_cols, nm);
         m->cols[l] = sample_members(nm, r, state);
         std::vector<double2> cols(r);
+        m->colk[l].resize(2 * (size_t)r);
         for (int c = 0; c < r; ++c) {
             const int om = members[l][m->cols[l][c]];
             cols[c] = make_double2(om / N - h, om % N - h);
+            m->colk[l][2 * c] = om / N - h;
+            m->colk[l][2 * c + 1] = om % N - h;
         }
         // joint Gram over the training scales
         std::vector<zd> Gsum((size_t)r * r, zd(0, 0));
@@ -652,7 +661,8 @@ fio_status fio_learned_generate(fio_learned_t m, int nscales, const double *scal
             const long long g = (long long)si * L + l;
             const unsigned long long key = splitmix64(m->seed + 0x9E37ull * (unsigned long long)(g + 1));
             k_make_samples<<<(x_samples + 255) / 256, 256>>>(ph, N, thetas[l], scales[si], d_cols, r, d_V, inv_s1,
-                                                             key, x_samples, m->d_feat + g * x_samples * kNetIn,
+                                                             key, x_samples, nullptr,
+                                                             m->d_feat + g * x_samples * kNetIn,
                                                              m->d_target + g * x_samples * kNetOut);
             FIO_HIP_TRY(hipGetLastError());
         }
@@ -769,6 +779,92 @@ fio_status fio_learned_eval(fio_learned_t m, double *loss) {
         sum += l * n;
     }
     *loss = sum / (double)m->nsamples;
+    return FIO_OK;
+}
+
+fio_status fio_learned_basis(fio_learned_t m, int ell, int cap, int *r, double *cols, double *V, double *s1) {
+    set_error("");
+    if (!m || !r || !s1 || cap < 0 || (cap > 0 && (!cols || !V)))
+        return (set_error("bad argument"), FIO_EINVAL);
+    if (ell < 0 || ell >= (int)m->colk.size())
+        return (set_error("wedge out of range, or no training data generated"), FIO_EINVAL);
+    const int rr = (int)m->colk[ell].size() / 2;
+    *r = rr;
+    *s1 = m->s1[ell];
+    if (rr > cap)
+        return (set_error("capacity below the column count"), FIO_EINVAL);
+    for (int c = 0; c < rr; ++c) {
+        cols[2 * c] = m->colk[ell][2 * c];
+        cols[2 * c + 1] = m->colk[ell][2 * c + 1];
+        for (int t = 0; t < kNetRank; ++t) {
+            const zd v = m->V[ell][(size_t)c * kNetRank + t];
+            V[2 * ((size_t)c * kNetRank + t)] = v.real();
+            V[2 * ((size_t)c * kNetRank + t) + 1] = v.imag();
+        }
+    }
+    return FIO_OK;
+}
+
+fio_status fio_learned_targets(fio_learned_t m, int ell, double scale, int nx, const long long *xidx, float *out) {
+    set_error("");
+    if (!m || nx < 0 || (nx > 0 && (!xidx || !out)))
+        return (set_error("bad argument"), FIO_EINVAL);
+    if (ell < 0 || ell >= (int)m->colk.size() || m->colk[ell].empty())
+        return (set_error("wedge out of range, or no training data generated"), FIO_EINVAL);
+    const long long NN = (long long)m->N * m->N;
+    for (int i = 0; i < nx; ++i)
+        if (xidx[i] < 0 || xidx[i] >= NN)
+            return (set_error("grid index out of range"), FIO_EINVAL);
+    if (nx == 0)
+        return FIO_OK;
+    const int r = (int)m->colk[ell].size() / 2;
+    std::vector<double2> cols(r);
+    for (int c = 0; c < r; ++c)
+        cols[c] = make_double2(m->colk[ell][2 * c], m->colk[ell][2 * c + 1]);
+    struct G {
+        std::vector<void *> p;
+        ~G() {
+            for (void *v : p)
+                if (v)
+                    (void)hipFree(v);
+        }
+    } guard;
+    double2 *d_cols = nullptr, *d_V = nullptr;
+    long long *d_x = nullptr;
+    float *d_t = nullptr;
+    FIO_HIP_TRY(hipMalloc(&d_cols, r * sizeof(double2)));
+    guard.p.push_back(d_cols);
+    FIO_HIP_TRY(hipMalloc(&d_V, (size_t)r * kNetRank * sizeof(double2)));
+    guard.p.push_back(d_V);
+    FIO_HIP_TRY(hipMalloc(&d_x, sizeof(long long) * nx));
+    guard.p.push_back(d_x);
+    FIO_HIP_TRY(hipMalloc(&d_t, sizeof(float) * (size_t)nx * kNetOut));
+    guard.p.push_back(d_t);
+    FIO_HIP_TRY(hipMemcpy(d_cols, cols.data(), r * sizeof(double2), hipMemcpyHostToDevice));
+    FIO_HIP_TRY(hipMemcpy(d_V, m->V[ell].data(), (size_t)r * kNetRank * sizeof(double2), hipMemcpyHostToDevice));
+    FIO_HIP_TRY(hipMemcpy(d_x, xidx, sizeof(long long) * nx, hipMemcpyHostToDevice));
+    Phase ph = m->family;
+    ph.p[0] = scale;
+    const double inv_s1 = std::sqrt((double)NN) / m->s1[ell];
+    k_make_samples<<<(nx + 255) / 256, 256>>>(ph, m->N, m->theta[ell], scale, d_cols, r, d_V, inv_s1, 0ull, nx, d_x,
+                                              nullptr, d_t);
+    FIO_HIP_TRY(hipGetLastError());
+    FIO_HIP_TRY(hipMemcpy(out, d_t, sizeof(float) * (size_t)nx * kNetOut, hipMemcpyDeviceToHost));
+    return FIO_OK;
+}
+
+fio_status fio_learned_adam_step(fio_learned_t m, const float *grads, double lr) {
+    set_error("");
+    if (!m || !grads || !(lr > 0))
+        return (set_error("bad argument"), FIO_EINVAL);
+    FIO_HIP_TRY(hipMemcpy(m->d_g, grads, sizeof(float) * m->nparams, hipMemcpyHostToDevice));
+    m->adam_t += 1;
+    const float c1 = (float)(1 - std::pow(0.9, (double)m->adam_t));
+    const float c2 = (float)(1 - std::pow(0.999, (double)m->adam_t));
+    k_adam<<<(m->nparams + 255) / 256, 256>>>(m->d_p, m->d_m, m->d_v, m->d_g, m->nparams, (float)lr, 0.9f, 0.999f,
+                                             1e-8f, c1, c2, m->d_wb);
+    FIO_HIP_TRY(hipGetLastError());
+    FIO_HIP_TRY(hipDeviceSynchronize());
     return FIO_OK;
 }
 

@@ -30,6 +30,8 @@ struct LearnedModel {
     float *d_target = nullptr;         // [n][32]
     // per-wedge column samples and joint right singular vectors (targets)
     std::vector<std::vector<int>> cols;   // member positions per wedge
+    std::vector<std::vector<int>> colk;   // their centred frequencies, (k1, k2) interleaved
+    std::vector<double> theta;            // wedge centre angles
     std::vector<std::vector<zd>> V;       // r x 16 per wedge
     std::vector<double> s1;               // leading joint singular value per wedge
     // scratch of the training step

@@ -4,8 +4,9 @@
 // sequence is captured into a HIP graph.  The graph and the device tables are
 // cached in the first plan and replayed while the instance list (plans and
 // batch sizes) stays the same; new data pointers only refresh the argument
-// table.  Instance lists the fused path cannot take (mixed kernel widths, or a
-// batch larger than a plan's workspace) run instance after instance instead.
+// table.  Instance lists the fused path cannot take (mixed kernel widths, a
+// batch larger than a plan's workspace, or one plan listed twice, whose single
+// workspace cannot hold two instances at once) run instance after instance.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -28,7 +29,11 @@ struct MultiState {
     MultiTile *d_tiles = nullptr;
     hipStream_t cap = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // recorded after each replay, on the caller's stream
+    bool launched = false;
     ~MultiState() {
+        if (done)
+            (void)hipEventDestroy(done);
         if (exec)
             (void)hipGraphExecDestroy(exec);
         if (cap)
@@ -138,6 +143,7 @@ static fio_status build_state(MultiState &st, int n, const fio_plan_t *plans, co
                              : (size_t)interp_window_bytes<float>(q) + interp_gx_lds_bytes<float>(q);
         st.ml.lds_interp = std::max(st.ml.lds_interp, b);
     }
+    FIO_HIP_TRY(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
     // capture the three launches once
     FIO_HIP_TRY(hipStreamCreateWithFlags(&st.cap, hipStreamNonBlocking));
     FIO_HIP_TRY(hipStreamBeginCapture(st.cap, hipStreamCaptureModeThreadLocal));
@@ -162,6 +168,11 @@ fio_status multi_apply(int n, const fio_plan_t *plans, const void *const *fhat, 
     for (int i = 0; i < n; ++i)
         if (plans[i]->w != plans[0]->w || plans[i]->regen != plans[0]->regen || B[i] > plans[i]->bchunk)
             fused = false;
+    // a plan listed twice would have both instances in its one workspace at once
+    for (int i = 0; fused && i < n; ++i)
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i])
+                fused = false;
     if (!fused)
         return run_sequential(n, plans, fhat, u, B, s);
     fio_plan_s *owner = plans[0];
@@ -189,8 +200,10 @@ fio_status multi_apply(int n, const fio_plan_t *plans, const void *const *fhat, 
     for (int i = 0; i < n; ++i)
         ptrs = ptrs && st->f[i] == fhat[i] && st->u[i] == u[i];
     if (!ptrs) {
-        // the previous replay may still read the argument table: let it finish
-        FIO_HIP_TRY(hipStreamSynchronize(s));
+        // the previous replay, on whichever stream it ran, may still read the
+        // argument table: wait for it before the table is overwritten
+        if (st->launched)
+            FIO_HIP_TRY(hipEventSynchronize(st->done));
         const size_t isz = inst_args_size(owner->precision);
         std::vector<unsigned char> host(isz * n);
         for (int i = 0; i < n; ++i) {
@@ -201,6 +214,8 @@ fio_status multi_apply(int n, const fio_plan_t *plans, const void *const *fhat, 
         FIO_HIP_TRY(hipMemcpy(st->d_inst, host.data(), host.size(), hipMemcpyHostToDevice));
     }
     FIO_HIP_TRY(hipGraphLaunch(st->exec, s));
+    FIO_HIP_TRY(hipEventRecord(st->done, s));
+    st->launched = true;
     return FIO_OK;
 }
 

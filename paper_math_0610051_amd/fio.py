@@ -106,6 +106,9 @@ def load_library():
         "fio_learned_param_count": (c_int, []),
         "fio_learned_forward": (c_int, [P, c_int, P, P]),
         "fio_learned_grads": (c_int, [P, c_int, P, P, P, P]),
+        "fio_learned_basis": (c_int, [P, c_int, c_int, P, P, P, P]),
+        "fio_learned_targets": (c_int, [P, c_int, c_double, c_int, P, P]),
+        "fio_learned_adam_step": (c_int, [P, P, c_double]),
         "fio_learned_save": (c_int, [P, c_char_p]),
         "fio_learned_load": (c_int, [c_char_p, POINTER(P)]),
         "fio_learned_destroy": (c_int, [P]),
@@ -427,6 +430,33 @@ class Learned:
         _check(self._lib.fio_learned_grads(self.handle, f.shape[0], f.ctypes.data, t.ctypes.data, g.ctypes.data,
                                            ctypes.byref(loss)))
         return g, loss.value
+
+    def basis(self, ell):
+        """(cols (r, 2) centred frequencies, V (r, 16) complex, s1) of wedge ell's targets."""
+        cap = 256
+        cols = np.empty(2 * cap)
+        V = np.empty(32 * cap)
+        r = ctypes.c_int()
+        s1 = ctypes.c_double()
+        _check(self._lib.fio_learned_basis(self.handle, int(ell), cap, ctypes.byref(r), cols.ctypes.data,
+                                           V.ctypes.data, ctypes.byref(s1)))
+        n = r.value
+        Vc = V[:32 * n].reshape(n, 16, 2)
+        return cols[:2 * n].reshape(n, 2).astype(np.int64), Vc[..., 0] + 1j * Vc[..., 1], s1.value
+
+    def targets(self, ell, scale, xidx):
+        """Training targets of wedge ell at phase scale `scale` at flat grid indices, (n, 32) float32."""
+        x = np.ascontiguousarray(np.asarray(xidx, dtype=np.int64))
+        out = np.empty((x.size, 32), dtype=np.float32)
+        _check(self._lib.fio_learned_targets(self.handle, int(ell), float(scale), x.size, x.ctypes.data,
+                                             out.ctypes.data))
+        return out
+
+    def adam_step(self, grads, lr):
+        g = np.ascontiguousarray(np.asarray(grads, dtype=np.float32))
+        if g.size != self.param_count():
+            raise ValueError("gradient vector of the wrong size")
+        _check(self._lib.fio_learned_adam_step(self.handle, g.ctypes.data, float(lr)))
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
