@@ -10,7 +10,8 @@
  *     (Lf)(x) = (1/N) sum_{xi in Omega} a(x,xi) exp(2 pi i Phi(x,xi)) fhat(xi),
  *
  * with X = {(n1/N, n2/N)}, Omega = [-N/2, N/2)^2, a = 1 (the Egorov form of
- * Section 3, eq. (Egorov)), and Phi(x,xi) = x.xi + h(x,xi) with h
+ * Section 3, eq. (Egorov)) or the Bessel amplitude of Section 4 (see
+ * oracle_amp), and Phi(x,xi) = x.xi + h(x,xi) with h
  * homogeneous of degree one in xi.  The phase families are:
  *   0 linear shift   h = p0 xi1 + p1 xi2               (exact translation)
  *   1 wave           h = p0 |xi|                       (Section 1, Phi_pm = x.xi +- c|xi|t)
@@ -81,6 +82,41 @@ static double oracle_h(int kind, const double *p, double x1, double x2, double k
     }
 }
 
+/*
+ * Amplitudes a(x, xi).  0: a = 1 (the Egorov form).  1: the Bessel amplitude
+ * of the integration along ellipses (Section 4, eq. (ellipses_amp), the '+'
+ * sign), a = (1/4pi) (J0(2 pi rho) + i Y0(2 pi rho)) exp(-2 pi i rho) with
+ * rho = h(x, xi) >= 0, taken as 0 at xi = 0, where Y0 is singular and the
+ * paper states no value.  J0 and Y0 are the C library's.
+ */
+static void oracle_amp(int amp, double hv, double k1, double k2, double *ar, double *ai)
+{
+    if (amp == 0) {
+        *ar = 1.0;
+        *ai = 0.0;
+        return;
+    }
+    if (k1 == 0.0 && k2 == 0.0) {
+        *ar = *ai = 0.0;
+        return;
+    }
+    const double z = TWO_PI * hv;
+    const double jr = j0(z), yi = y0(z);
+    const double r = hv - rint(hv);
+    const double c = cos(TWO_PI * r), sn = -sin(TWO_PI * r);
+    const double s4 = 1.0 / (2.0 * TWO_PI);
+    *ar = s4 * (jr * c - yi * sn);
+    *ai = s4 * (jr * sn + yi * c);
+}
+
+/* a only, for tests of the amplitude: out[2i], out[2i+1] = a(x_i, xi_i). */
+void oracle_amp_batch(int kind, const double *p, int amp, int n, const double *x1, const double *x2,
+                      const double *k1, const double *k2, double *out)
+{
+    for (int i = 0; i < n; ++i)
+        oracle_amp(amp, oracle_h(kind, p, x1[i], x2[i], k1[i], k2[i]), k1[i], k2[i], out + 2 * i, out + 2 * i + 1);
+}
+
 /* h only, for tests of the phase families: out[i] = h(x_i, xi_i). */
 void oracle_h_batch(int kind, const double *p, int n, const double *x1, const double *x2,
                     const double *k1, const double *k2, double *out)
@@ -101,8 +137,8 @@ void oracle_h_batch(int kind, const double *p, int n, const double *x1, const do
  *   u     : ns*nrhs complex (interleaved) output
  * Returns 0, or -1 on bad arguments.
  */
-int oracle_direct(int N, int kind, const double *p, int ns, const int64_t *xidx, int nrhs,
-                  const double *fhat, const int32_t *member, int only, double *u, int nthreads)
+int oracle_direct_amp(int N, int kind, const double *p, int amp, int ns, const int64_t *xidx, int nrhs,
+                      const double *fhat, const int32_t *member, int only, double *u, int nthreads)
 {
     if (N <= 0 || (N & 1) || ns < 0 || nrhs <= 0 || nrhs > 64)
         return -1;
@@ -132,15 +168,25 @@ int oracle_direct(int N, int kind, const double *p, int ns, const int64_t *xidx,
                 int64_t ip = (n1 * k1 + n2 * k2) % N;
                 if (ip < 0)
                     ip += N;
-#if defined(ORACLE_PLANT) && ORACLE_PLANT == 1
-                double ph = (double)ip / N - oracle_h(kind, p, x1, x2, (double)k1, (double)k2);
-#elif defined(ORACLE_PLANT) && ORACLE_PLANT == 3
-                double ph = (double)ip / N + oracle_h(kind, p, x2, x1, (double)k1, (double)k2);
+#if defined(ORACLE_PLANT) && ORACLE_PLANT == 3
+                const double hv = oracle_h(kind, p, x2, x1, (double)k1, (double)k2);
 #else
-                double ph = (double)ip / N + oracle_h(kind, p, x1, x2, (double)k1, (double)k2);
+                const double hv = oracle_h(kind, p, x1, x2, (double)k1, (double)k2);
+#endif
+#if defined(ORACLE_PLANT) && ORACLE_PLANT == 1
+                double ph = (double)ip / N - hv;
+#else
+                double ph = (double)ip / N + hv;
 #endif
                 double r = ph - rint(ph);
                 double c = cos(TWO_PI * r), sn = sin(TWO_PI * r);
+                if (amp) {
+                    double ar, ai;
+                    oracle_amp(amp, hv, (double)k1, (double)k2, &ar, &ai);
+                    const double cr = c * ar - sn * ai, ci = c * ai + sn * ar;
+                    c = cr;
+                    sn = ci;
+                }
                 for (int b = 0; b < nrhs; ++b) {
                     const double *f = fhat + 2 * ((int64_t)b * N * N + cell);
                     row_re[b] += c * f[0] - sn * f[1];
@@ -165,6 +211,13 @@ int oracle_direct(int N, int kind, const double *p, int ns, const int64_t *xidx,
     return 0;
 }
 
+/* The Egorov form a = 1. */
+int oracle_direct(int N, int kind, const double *p, int ns, const int64_t *xidx, int nrhs, const double *fhat,
+                  const int32_t *member, int only, double *u, int nthreads)
+{
+    return oracle_direct_amp(N, kind, p, 0, ns, xidx, nrhs, fhat, member, only, u, nthreads);
+}
+
 /*
  * Adjoint (Section 3.5): the Fourier coefficients of L*g,
  *
@@ -179,8 +232,8 @@ int oracle_direct(int N, int kind, const double *p, int ns, const int64_t *xidx,
  * reduction by the nearest integer, FP64 accumulation summed per row of y.
  * Returns 0, or -1 on bad arguments.
  */
-int oracle_direct_adjoint(int N, int kind, const double *p, int ns, const int64_t *xiidx, int nrhs,
-                          const double *g, double *hhat, int nthreads)
+int oracle_direct_adjoint_amp(int N, int kind, const double *p, int amp, int ns, const int64_t *xiidx, int nrhs,
+                              const double *g, double *hhat, int nthreads)
 {
     if (N <= 0 || (N & 1) || ns < 0 || nrhs <= 0 || nrhs > 64)
         return -1;
@@ -207,13 +260,21 @@ int oracle_direct_adjoint(int N, int kind, const double *p, int ns, const int64_
                 int64_t ip = ((int64_t)n1 * k1 + (int64_t)n2 * k2) % N;
                 if (ip < 0)
                     ip += N;
-                double ph = (double)ip / N + oracle_h(kind, p, x1, x2, (double)k1, (double)k2);
+                const double hv = oracle_h(kind, p, x1, x2, (double)k1, (double)k2);
+                double ph = (double)ip / N + hv;
 #if defined(ORACLE_PLANT) && ORACLE_PLANT == 6
                 ph = -ph;
 #endif
                 double r = ph - rint(ph);
-                /* exp(-2 pi i r) */
+                /* conj(a) exp(-2 pi i r) */
                 double c = cos(TWO_PI * r), sn = -sin(TWO_PI * r);
+                if (amp) {
+                    double ar, ai;
+                    oracle_amp(amp, hv, (double)k1, (double)k2, &ar, &ai);
+                    const double cr = c * ar + sn * ai, ci = sn * ar - c * ai;
+                    c = cr;
+                    sn = ci;
+                }
                 const int64_t cell = (int64_t)n1 * N + n2;
                 for (int b = 0; b < nrhs; ++b) {
                     const double *v = g + 2 * ((int64_t)b * N * N + cell);
@@ -232,6 +293,12 @@ int oracle_direct_adjoint(int N, int kind, const double *p, int ns, const int64_
         }
     }
     return 0;
+}
+
+int oracle_direct_adjoint(int N, int kind, const double *p, int ns, const int64_t *xiidx, int nrhs, const double *g,
+                          double *hhat, int nthreads)
+{
+    return oracle_direct_adjoint_amp(N, kind, p, 0, ns, xiidx, nrhs, g, hhat, nthreads);
 }
 
 /* Number of OpenMP threads a parallel region would use (1 without OpenMP). */

@@ -49,6 +49,17 @@ def _load(path: str | None = None):
         lib.oracle_direct.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_direct_amp.restype = ctypes.c_int
+        lib.oracle_direct_amp.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_direct_adjoint_amp.restype = ctypes.c_int
+        lib.oracle_direct_adjoint_amp.argtypes = [
+            ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+        lib.oracle_amp_batch.restype = None
+        lib.oracle_amp_batch.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int] + \
+            [ctypes.c_void_p] * 5
         lib.oracle_direct_adjoint.restype = ctypes.c_int
         lib.oracle_direct_adjoint.argtypes = [
             ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
@@ -71,6 +82,16 @@ def max_threads() -> int:
     return int(_load().oracle_max_threads())
 
 
+def amp_values(kind: int, params, amp: int, x1, x2, k1, k2) -> np.ndarray:
+    """a(x, xi) from the C oracle at paired points (complex)."""
+    x1, x2, k1, k2 = (np.ascontiguousarray(np.asarray(a, dtype=np.float64).ravel()) for a in (x1, x2, k1, k2))
+    out = np.empty(2 * x1.size)
+    p = _params(params)
+    _load().oracle_amp_batch(int(kind), p.ctypes.data, int(amp), x1.size, x1.ctypes.data, x2.ctypes.data,
+                             k1.ctypes.data, k2.ctypes.data, out.ctypes.data)
+    return out[0::2] + 1j * out[1::2]
+
+
 def h_values(kind: int, params, x1, x2, k1, k2) -> np.ndarray:
     """h(x, xi) from the C oracle at paired points (for cross-checking families)."""
     x1, x2, k1, k2 = (np.ascontiguousarray(np.asarray(a, dtype=np.float64).ravel()) for a in (x1, x2, k1, k2))
@@ -82,11 +103,12 @@ def h_values(kind: int, params, x1, x2, k1, k2) -> np.ndarray:
 
 
 def direct(N: int, kind: int, params, fhat, xidx, member=None, only: int = 0, threads: int = 0,
-           lib_path: str | None = None) -> np.ndarray:
+           lib_path: str | None = None, amp: int = 0) -> np.ndarray:
     """(Lf)(x) at flat sample indices `xidx` by FP64 direct summation (eq. dfio).
 
     fhat: (N, N) or (B, N, N) complex, centred layout.  Returns (ns,) or
-    (B, ns) complex128.  `member`/`only` restrict the sum to one wedge.
+    (B, ns) complex128.  `member`/`only` restrict the sum to one wedge;
+    amp = 1 selects the Bessel amplitude of Section 4 (a = 1 otherwise).
     """
     fh = np.asarray(fhat)
     single = fh.ndim == 2
@@ -103,9 +125,9 @@ def direct(N: int, kind: int, params, fhat, xidx, member=None, only: int = 0, th
         nb = min(64, B - b0)
         part = np.empty((xs.size, nb), dtype=np.complex128)
         chunk = np.ascontiguousarray(fh[b0:b0 + nb])
-        rc = lib.oracle_direct(int(N), int(kind), p.ctypes.data, xs.size, xs.ctypes.data, nb,
-                               chunk.ctypes.data, None if mem is None else mem.ctypes.data, int(only),
-                               part.ctypes.data, int(threads))
+        rc = lib.oracle_direct_amp(int(N), int(kind), p.ctypes.data, int(amp), xs.size, xs.ctypes.data, nb,
+                                   chunk.ctypes.data, None if mem is None else mem.ctypes.data, int(only),
+                                   part.ctypes.data, int(threads))
         if rc != 0:
             raise ValueError("oracle_direct rejected its arguments")
         out[:, b0:b0 + nb] = part
@@ -113,7 +135,8 @@ def direct(N: int, kind: int, params, fhat, xidx, member=None, only: int = 0, th
     return out[0] if single else out
 
 
-def direct_adjoint(N: int, kind: int, params, g, xiidx, threads: int = 0, lib_path: str | None = None) -> np.ndarray:
+def direct_adjoint(N: int, kind: int, params, g, xiidx, threads: int = 0, lib_path: str | None = None,
+                   amp: int = 0) -> np.ndarray:
     """Fourier coefficients of L*g at flat centred frequency indices `xiidx`
     by FP64 direct summation (Section 3.5):
     hhat(xi) = (1/N) sum_y exp(-2 pi i Phi(y, xi)) g(y).
@@ -133,8 +156,8 @@ def direct_adjoint(N: int, kind: int, params, g, xiidx, threads: int = 0, lib_pa
         nb = min(64, B - b0)
         part = np.empty((ks.size, nb), dtype=np.complex128)
         chunk = np.ascontiguousarray(ga[b0:b0 + nb])
-        rc = lib.oracle_direct_adjoint(int(N), int(kind), p.ctypes.data, ks.size, ks.ctypes.data, nb,
-                                       chunk.ctypes.data, part.ctypes.data, int(threads))
+        rc = lib.oracle_direct_adjoint_amp(int(N), int(kind), p.ctypes.data, int(amp), ks.size, ks.ctypes.data,
+                                           nb, chunk.ctypes.data, part.ctypes.data, int(threads))
         if rc != 0:
             raise ValueError("oracle_direct_adjoint rejected its arguments")
         out[:, b0:b0 + nb] = part

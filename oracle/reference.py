@@ -111,6 +111,23 @@ def grad_h(kind, p, x1, x2, e1, e2):
     return p[0] * a * a * e1 / q, p[0] * b * b * e2 / q
 
 
+def amplitude(kind, p, amp, x1, x2, k1, k2):
+    """a(x, xi): 1 (amp = 0), or the Bessel amplitude of Section 4 (amp = 1),
+    a = (1/4 pi)(J0(2 pi rho) + i Y0(2 pi rho)) exp(-2 pi i rho) with rho =
+    h(x, xi) >= 0, and a = 0 at xi = 0 (Y0 is singular there; the paper
+    states no value).  J0 and Y0 from scipy.special."""
+    from scipy import special
+    k1 = np.asarray(k1, float)
+    k2 = np.asarray(k2, float)
+    if amp == 0:
+        return np.ones(np.broadcast(np.asarray(x1), k1, k2).shape, dtype=complex)
+    rho = h(kind, p, x1, x2, k1, k2)
+    origin = (k1 == 0) & (k2 == 0)
+    z = 2 * np.pi * np.where(origin, 1.0, rho)
+    a = (special.j0(z) + 1j * special.y0(z)) * _expi(-rho) / (4 * np.pi)
+    return np.where(origin, 0.0, a)
+
+
 def phase(kind, p, x1, x2, k1, k2):
     """Phi(x, xi) = x.xi + h(x, xi) in FP64."""
     return np.asarray(x1) * k1 + np.asarray(x2) * k2 + h(kind, p, x1, x2, k1, k2)
@@ -141,10 +158,11 @@ def apply_dense(N, kind, p, fhat):
     return (kernel_matrix(N, kind, p) @ np.asarray(fhat).reshape(N * N)).reshape(N, N)
 
 
-def direct(N, kind, p, fhat, xidx, member=None, only=0, chunk=64):
+def direct(N, kind, p, fhat, xidx, member=None, only=0, chunk=64, amp=0):
     """(Lf)(x) at flat indices `xidx` by FP64 direct sum over Omega (or one wedge).
 
     Independent of the C oracle: vectorised NumPy with a per-chunk matrix.
+    amp = 1 multiplies the kernel by the Bessel amplitude (`amplitude`).
     """
     fh = np.asarray(fhat, dtype=np.complex128).reshape(N * N)
     k1, k2 = grid_xi(N)
@@ -156,7 +174,10 @@ def direct(N, kind, p, fhat, xidx, member=None, only=0, chunk=64):
     for s in range(0, x1.size, chunk):
         a1 = x1[s:s + chunk, None]
         a2 = x2[s:s + chunk, None]
-        out[s:s + chunk] = _expi(phase(kind, p, a1, a2, k1[None, :], k2[None, :])) @ fh / N
+        K = _expi(phase(kind, p, a1, a2, k1[None, :], k2[None, :]))
+        if amp:
+            K = K * amplitude(kind, p, amp, a1, a2, k1[None, :], k2[None, :])
+        out[s:s + chunk] = K @ fh / N
     return out
 
 
