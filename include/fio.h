@@ -170,6 +170,19 @@ fio_status fio_apply(fio_plan_t plan, const void *fhat, void *u, void *stream);
  * points and kernel weights are shared across the batch. */
 fio_status fio_apply_batch(fio_plan_t plan, int B, const void *fhat, void *u, void *stream);
 
+/* fio_apply_batch for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * It calls no allocating routine: the row-stage output and the oversampled
+ * grids, which fio_apply_batch keeps in the plan's workspace, live in a fixed
+ * 128 MiB device array of the library instead (one per device, held until
+ * the process ends).  Same kernels and results as fio_apply_batch, bit for
+ * bit.  Right-hand sides are processed in as many passes as the array needs;
+ * FIO_EINVAL if one right-hand side does not fit (about N <= 256 at tol 1e-4
+ * fits).  Every call on a device shares that device's array: calls that
+ * overlap on one device (two streams, two threads) race and must not be
+ * issued.  The plan's own workspace is not touched. */
+fio_status fio_apply_batch_noalloc(fio_plan_t plan, int B, const void *fhat, void *u, void *stream);
+
 /* n instances of possibly different N (each its own plan, all of one
  * precision), instance i with B[i] right-hand sides at fhat[i] -> u[i] (host
  * arrays of device pointers).  All instances, wedges and right-hand sides run

@@ -245,6 +245,27 @@ fio_status fio_apply_batch(fio_plan_t plan, int B, const void *fhat, void *u, vo
     return apply_common(plan, 0, plan ? plan->L : 0, B, fhat, u, stream);
 }
 
+fio_status fio_apply_batch_noalloc(fio_plan_t P, int B, const void *fhat, void *u, void *stream) {
+    set_error("");
+    if (!P || !fhat || !u)
+        return (set_error("null argument"), FIO_EINVAL);
+    if (B < 1)
+        return (set_error("B must be >= 1"), FIO_EINVAL);
+    const long long per = scratch_bytes_per_rhs(P);
+    if (per + 256 > (long long)kScratchBytes) {
+        char msg[200];
+        std::snprintf(msg, sizeof(msg),
+                      "one right-hand side needs %lld bytes of scratch, above the fixed %lld-byte array", per + 256,
+                      (long long)kScratchBytes);
+        return (set_error(msg), FIO_EINVAL);
+    }
+    DeviceScope ds(P->device);
+    if (ds.err != hipSuccess)
+        return hip_fail(ds.err, "hipSetDevice");
+    FIO_HIP_TRY(apply_launch_scratch(P, B, fhat, u, static_cast<hipStream_t>(stream)));
+    return FIO_OK;
+}
+
 fio_status fio_apply_wedges(fio_plan_t plan, int l0, int l1, int B, const void *fhat, void *u, void *stream) {
     return apply_common(plan, l0, l1, B, fhat, u, stream);
 }

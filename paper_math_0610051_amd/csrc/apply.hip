@@ -16,6 +16,7 @@
 #include <climits>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 
 #include "apply.hpp"
 
@@ -926,7 +927,7 @@ struct StageTimer {
     hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
     StageTimer(fio_plan_s *P_, int stage_, hipStream_t s_) : P(P_), stage(stage_), s(s_) {
-        if (P->profiling && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+        if (P && P->profiling && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
             (void)hipEventRecord(a, s);
     }
     ~StageTimer() {
@@ -942,25 +943,44 @@ struct StageTimer {
     }
 };
 
+// One apply of B right-hand sides over wedges [l0, l1).  The row-stage output
+// H and the grids G live in the plan's workspace, or, when `ws` is given, in
+// the caller-provided device region ws (wsb bytes): H of `chunk` right-hand
+// sides, then G of as many at the next 256-byte boundary, where chunk is what
+// fits (at most the plan's batch chunk).  Every cell of H and G is written
+// before it is read, so the region needs no clearing.  No events are created
+// on the ws path.
 template <typename T>
-static hipError_t apply_t(fio_plan_s *P, int B, const void *fhat, void *u, hipStream_t s, int l0, int l1) {
-    const PlanArgs<T> a = make_args<T>(P);
+static hipError_t apply_t(fio_plan_s *P, int B, const void *fhat, void *u, hipStream_t s, int l0, int l1,
+                          void *ws = nullptr, size_t wsb = 0) {
+    PlanArgs<T> a = make_args<T>(P);
+    int chunk = P->bchunk;
+    if (ws) {
+        const long long per = (long long)sizeof(cplx<T>) * (P->H_total + P->G_total);
+        chunk = (int)std::min<long long>(P->bchunk, per > 0 ? (long long)(wsb - 256) / per : P->bchunk);
+        if (chunk < 1)
+            return hipErrorInvalidValue;
+        const size_t hb = ((size_t)sizeof(cplx<T>) * P->H_total * chunk + 255) & ~size_t(255);
+        a.H = static_cast<cplx<T> *>(ws);
+        a.G = reinterpret_cast<cplx<T> *>(static_cast<unsigned char *>(ws) + hb);
+    }
+    const bool timed = ws == nullptr;
     const long long NN = (long long)P->N * P->N;
     const cplx<T> *f = static_cast<const cplx<T> *>(fhat);
     cplx<T> *out = static_cast<cplx<T> *>(u);
     const int r0 = P->row_first[l0], r1 = P->row_first[l1];
     const int c0 = P->col_first[l0], c1 = P->col_first[l1];
-    for (int b0 = 0; b0 < B; b0 += P->bchunk) {
-        const int bc = std::min(P->bchunk, B - b0);
+    for (int b0 = 0; b0 < B; b0 += chunk) {
+        const int bc = std::min(chunk, B - b0);
         if (r1 > r0) {
-            StageTimer tm(P, 0, s);
+            StageTimer tm(timed ? P : nullptr, 0, s);
             k_rows<T><<<r1 - r0, kFftThreads, P->lds_rows, s>>>(a, P->d_rows + r0, f + b0 * NN, NN, bc);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess)
                 return e;
         }
         if (c1 > c0) {
-            StageTimer tm(P, 1, s);
+            StageTimer tm(timed ? P : nullptr, 1, s);
             k_cols<T><<<dim3(c1 - c0, bc), kColThreads, P->lds_cols, s>>>(a, P->d_cols + c0);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess)
@@ -968,7 +988,7 @@ static hipError_t apply_t(fio_plan_s *P, int B, const void *fhat, void *u, hipSt
         }
         for (int bs = 0; bs < bc; bs += kInterpBatch) {
             const int nb = std::min(kInterpBatch, bc - bs);
-            StageTimer tm(P, 2, s);
+            StageTimer tm(timed ? P : nullptr, 2, s);
             hipError_t e = launch_interp<T>(P, a, out + (b0 + bs) * NN, NN, nb, bs, l0, l1, s);
             if (e != hipSuccess)
                 return e;
@@ -1104,6 +1124,52 @@ hipError_t apply_launch(fio_plan_s *P, int B, const void *fhat, void *u, hipStre
     if (P->precision == FIO_F64)
         return apply_t<double>(P, B, fhat, u, s, l0, l1);
     return apply_t<float>(P, B, fhat, u, s, l0, l1);
+}
+
+// ---------------------------------------------------------------------------
+// The apply without allocation.  Its H and G live in `scratch`, a fixed
+// device array of this file (one copy per device, held until the process
+// ends).  In host code `scratch` names a host-side stand-in, so kernels get
+// its device address from hipGetSymbolAddress, taken once per device with
+// that device current and kept in scratch_ptr.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t scratch_address(int device, void **out) {
+    if (device < 0 || device >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        if (!p)
+            return hipErrorInvalidSymbol;
+        scratch_ptr[device] = p;
+    }
+    *out = scratch_ptr[device];
+    return hipSuccess;
+}
+
+long long scratch_bytes_per_rhs(const fio_plan_s *P) {
+    return (long long)P->esize * (P->H_total + P->G_total);
+}
+
+hipError_t apply_launch_scratch(fio_plan_s *P, int B, const void *fhat, void *u, hipStream_t s) {
+    void *ws = nullptr;
+    const hipError_t e = scratch_address(P->device, &ws);
+    if (e != hipSuccess)
+        return e;
+    if (P->precision == FIO_F64)
+        return apply_t<double>(P, B, fhat, u, s, 0, P->L, ws, kScratchBytes);
+    return apply_t<float>(P, B, fhat, u, s, 0, P->L, ws, kScratchBytes);
 }
 
 }  // namespace fio

@@ -102,4 +102,10 @@ hipError_t apply_prepare(fio_plan_s *P);
 hipError_t zero_fill(void *ptr, size_t bytes, hipStream_t s);
 hipError_t apply_launch(fio_plan_s *P, int B, const void *fhat, void *u, hipStream_t s, int l0, int l1);
 
+// The apply without allocation: H and G in a fixed device array of
+// kScratchBytes per device instead of the plan's workspace.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+long long scratch_bytes_per_rhs(const fio_plan_s *P);  // H + G of one right-hand side
+hipError_t apply_launch_scratch(fio_plan_s *P, int B, const void *fhat, void *u, hipStream_t s);
+
 }  // namespace fio

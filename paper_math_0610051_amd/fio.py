@@ -88,6 +88,7 @@ def load_library():
         "fio_apply_batch": (c_int, [P, c_int, P, P, P]),
         "fio_apply_multi": (c_int, [c_int, POINTER(P), POINTER(P), POINTER(P), POINTER(c_int), P]),
         "fio_apply_wedges": (c_int, [P, c_int, c_int, c_int, P, P, P]),
+        "fio_apply_batch_noalloc": (c_int, [P, c_int, P, P, P]),
         "fio_plan_info": (c_int, [P, POINTER(fio_plan_info_t)]),
         "fio_wedge_info": (c_int, [P, c_int, POINTER(fio_wedge_info_t)]),
         "fio_wedge_map": (c_int, [P, P]),
@@ -272,6 +273,16 @@ class Plan:
         fhat, out, B, stream = self._io(fhat, out)
         _check(self._lib.fio_apply_batch(self.handle, B, c_void_p(fhat.data_ptr()), c_void_p(out.data_ptr()),
                                          c_void_p(stream)))
+        return out
+
+    def apply_noalloc(self, fhat, out):
+        """fio_apply_batch_noalloc: u = L fhat into the caller's `out`, with the
+        library's fixed scratch array in place of the plan's workspace."""
+        if out is None:
+            raise ValueError("apply_noalloc writes into a caller-provided out")
+        fhat, out, B, stream = self._io(fhat, out)
+        _check(self._lib.fio_apply_batch_noalloc(self.handle, B, c_void_p(fhat.data_ptr()),
+                                                 c_void_p(out.data_ptr()), c_void_p(stream)))
         return out
 
     def apply_wedges(self, l0, l1, fhat, out=None):
