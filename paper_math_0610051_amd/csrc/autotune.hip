@@ -23,7 +23,7 @@
 
 namespace fio {
 
-// One block per sample point: u(x) = (1/N) sum_xi exp(2 pi i Phi(x, xi)) fhat(xi),
+// One block per sample point: u(x) = (1/N) sum_xi a(x, xi) exp(2 pi i Phi(x, xi)) fhat(xi),
 // x.xi reduced exactly in integers, h in FP64, FP64 accumulation.
 template <typename T>
 __global__ __launch_bounds__(256) void k_direct_probe(Phase ph, int N, const cplx<T> *__restrict__ fhat,
@@ -39,10 +39,18 @@ __global__ __launch_bounds__(256) void k_direct_probe(Phase ph, int N, const cpl
         long long ip = ((long long)n1 * k1 + (long long)n2 * k2) % N;
         if (ip < 0)
             ip += N;
-        double phs = (double)ip / N + phase_h(ph, c, (double)k1, (double)k2);
+        const double hv = phase_h(ph, c, (double)k1, (double)k2);
+        double phs = (double)ip / N + hv;
         phs -= rint(phs);
         double cs, sn;
         expi2pi(phs, cs, sn);
+        if (ph.amp == 1) {
+            double ar, ai;
+            amp_bessel(hv, k1 == 0 && k2 == 0, ar, ai);
+            const double tr = cs * ar - sn * ai;
+            sn = cs * ai + sn * ar;
+            cs = tr;
+        }
         const cplx<T> f = fhat[i];
         ar += cs * (double)f.re - sn * (double)f.im;
         ai += cs * (double)f.im + sn * (double)f.re;

@@ -74,6 +74,7 @@ __device__ inline void expi2pi_f(float r, float &c, float &s) { sincospif(2.0f *
 // ---------------------------------------------------------------------------
 struct Phase {
     int kind;
+    int amp;  // amplitude kind (fio.h): 0 a = 1, 1 the Bessel amplitude of Section 4
     double p[8];
 };
 
@@ -165,6 +166,48 @@ __host__ __device__ inline double residual_reduced(const Phase &ph, XCoef c, dou
                                                    double k2) {
     double r = phase_h(ph, c, k1, k2) - (g1 * k1 + g2 * k2);
     return r - rint(r);
+}
+
+// The Bessel amplitude of the integration along ellipses (Section 4, eq.
+// (ellipses_amp), '+' sign): a = (1/4pi)(J0(2 pi rho) + i Y0(2 pi rho))
+// exp(-2 pi i rho) with rho = h(x, xi) >= 0, and a = 0 at xi = 0, where Y0 is
+// singular (the paper states no value there).  J0 and Y0 are the math
+// library's (the device library on the GPU, the C library on the host).
+__host__ __device__ inline void amp_bessel(double rho, bool origin, double &ar, double &ai) {
+    if (origin) {
+        ar = ai = 0.0;
+        return;
+    }
+    const double z = kTwoPi * rho;
+#ifdef __HIP_DEVICE_COMPILE__
+    const double jr = j0(z), yi = y0(z);
+#else
+    const double jr = ::j0(z), yi = ::y0(z);
+#endif
+    double c, s;
+    expi2pi(rho - rint(rho), c, s);
+    const double k = 1.0 / (2.0 * kTwoPi);
+    ar = k * (jr * c + yi * s);  // (J0 + i Y0)(c - i s) / (4 pi)
+    ai = k * (yi * c - jr * s);
+}
+
+// Entry a(x, xi) exp(2 pi i Phi_ell(x, xi)) of the residual kernel of wedge
+// ell (Section 3.2, with the amplitude folded in as Section 4 describes),
+// given g = grad_xi h(x, xi_hat_ell); the phase is reduced by its nearest
+// integer before the exponential.
+__host__ __device__ inline void residual_entry(const Phase &ph, XCoef c, double g1, double g2, double k1, double k2,
+                                               double &re, double &im) {
+    const double hv = phase_h(ph, c, k1, k2);
+    double r = hv - (g1 * k1 + g2 * k2);
+    r -= rint(r);
+    expi2pi(r, re, im);
+    if (ph.amp == 1) {
+        double ar, ai;
+        amp_bessel(hv, k1 == 0.0 && k2 == 0.0, ar, ai);
+        const double tr = re * ar - im * ai;
+        im = re * ai + im * ar;
+        re = tr;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -256,9 +256,8 @@ __global__ void k_make_samples(Phase ph, int N, double theta, double s, const do
     for (int t = 0; t < kNetRank; ++t)
         ar[t] = ai[t] = 0;
     for (int k = 0; k < r; ++k) {
-        const double rr = residual_reduced(ph, c, g1, g2, cols[k].x, cols[k].y);
         double cs, sn;
-        expi2pi(rr, cs, sn);
+        residual_entry(ph, c, g1, g2, cols[k].x, cols[k].y, cs, sn);
 #pragma unroll
         for (int t = 0; t < kNetRank; ++t) {
             const double2 v = V[k * kNetRank + t];
@@ -278,6 +277,35 @@ __global__ void k_make_samples(Phase ph, int N, double theta, double s, const do
         target[(long long)i * kNetOut + 2 * t] = (float)(ar[t] * inv_s1);
         target[(long long)i * kNetOut + 2 * t + 1] = (float)(ai[t] * inv_s1);
     }
+}
+
+// Features of n given grid points (flat indices xs) at scale s; rows n .. npad
+// (the padding to a multiple of 64) repeat the last point.
+__global__ void k_point_features(int N, const long long *__restrict__ xs, int n, int npad, double theta, double s,
+                                 unsigned short *__restrict__ X) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad)
+        return;
+    const long long p = xs[i < n ? i : n - 1];
+    float f[kNetIn];
+    net_features((double)(p / N) / N, (double)(p % N) / N, theta, s, f);
+#pragma unroll
+    for (int k = 0; k < kNetIn; ++k)
+        X[(long long)i * kNetIn + k] = f2bf(f[k]);
+}
+
+// The leading ncols complex outputs of n rows of network outputs (32 floats
+// per row) into dst with row stride ld complex; columns ncols .. ld are zeroed.
+__global__ void k_take_factors(const float *__restrict__ Y, long long n, int ncols, int ld, float *__restrict__ dst) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * ld)
+        return;
+    const long long row = i / ld;
+    const int t = (int)(i - row * ld);
+    const float re = t < ncols ? Y[row * kNetOut + 2 * t] : 0.0f;
+    const float im = t < ncols ? Y[row * kNetOut + 2 * t + 1] : 0.0f;
+    dst[2 * i] = re;
+    dst[2 * i + 1] = im;
 }
 
 // Features of every grid point of one wedge at scale s (inference).
@@ -442,9 +470,9 @@ static hipError_t backward(LearnedModel *M, const StepBuffers &b, int n, double 
     return hipSuccess;
 }
 
-hipError_t learned_infer_wedge(LearnedModel *M, double theta, double s, void *out, int qpad, int precision,
+hipError_t learned_infer_wedge(LearnedModel *M, double theta, double s, void *out, int q, int qpad, int precision,
                                hipStream_t st) {
-    if (precision != FIO_F32 || qpad != kNetRank)
+    if (precision != FIO_F32 || q < 1 || q > kNetRank || qpad < q || qpad > kNetRank)
         return hipErrorInvalidValue;
     const long long NN = (long long)M->N * M->N;
     const int chunk = 1 << 16;
@@ -459,15 +487,41 @@ hipError_t learned_infer_wedge(LearnedModel *M, double theta, double s, void *ou
         k_grid_features<<<(npad + 255) / 256, 256, 0, st>>>(M->N, x0, npad, theta, s, b.X);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
-        // the output layer writes the interleaved (re, im) pairs of the 16 factors
-        if (n == npad) {
+        // the output layer writes the interleaved (re, im) pairs of the 16
+        // factors; the leading q are kept, at the plan's padded rank
+        if (n == npad && q == kNetRank && qpad == kNetRank) {
             e = forward(M, b, npad, false, Y + x0 * kNetOut, kNetOut, st);
         } else {
             e = forward(M, b, npad, false, b.Y, kNetOut, st);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(Y + x0 * kNetOut, b.Y, (size_t)n * kNetOut * sizeof(float),
-                                   hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess) {
+                const long long tot = (long long)n * qpad;
+                k_take_factors<<<(unsigned)((tot + 255) / 256), 256, 0, st>>>(b.Y, n, q, qpad, Y + x0 * 2 * qpad);
+                e = hipGetLastError();
+            }
         }
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t learned_infer_points(LearnedModel *M, double theta, double s, const long long *d_x, int n, float *d_out,
+                                hipStream_t st) {
+    const int chunk = 1 << 16;
+    hipError_t e = ensure_scratch(M, chunk);
+    if (e != hipSuccess)
+        return e;
+    StepBuffers b = carve(M, chunk);
+    for (int x0 = 0; x0 < n; x0 += chunk) {
+        const int m = std::min(chunk, n - x0);
+        const int npad = ((m + 63) / 64) * 64;
+        k_point_features<<<(npad + 255) / 256, 256, 0, st>>>(M->N, d_x + x0, m, npad, theta, s, b.X);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        e = forward(M, b, npad, false, b.Y, kNetOut, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_out + (size_t)x0 * kNetOut, b.Y, (size_t)m * kNetOut * sizeof(float),
+                               hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess)
             return e;
     }

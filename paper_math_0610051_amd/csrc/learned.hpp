@@ -42,9 +42,13 @@ struct LearnedModel {
     ~LearnedModel();
 };
 
-// Inference of alpha for all grid points of wedge ell at scale s into
-// out (N^2 x 16 complex, stride qpad), in the precision of the plan.
-hipError_t learned_infer_wedge(LearnedModel *M, double theta, double s, void *out, int qpad, int precision,
+// Inference of the leading q factors alpha_t for all grid points of wedge
+// ell at scale s into out (N^2 rows of qpad complex; columns q .. qpad
+// zeroed), in the precision of the plan (FP32 only).
+hipError_t learned_infer_wedge(LearnedModel *M, double theta, double s, void *out, int q, int qpad, int precision,
                                hipStream_t st);
+// All 16 factors at n given grid points (device index list) into d_out (n x 32 floats).
+hipError_t learned_infer_points(LearnedModel *M, double theta, double s, const long long *d_x, int n, float *d_out,
+                                hipStream_t st);
 
 }  // namespace fio

@@ -206,13 +206,12 @@ __global__ void k_xcoef(Phase ph, int N, double2 *out) {
     out[p] = make_double2(c.a, c.b);
 }
 
-__device__ inline double2 residual_entry(const Phase &ph, double2 xc, double e1, double e2, double k1, double k2) {
+__device__ inline double2 residual_at(const Phase &ph, double2 xc, double e1, double e2, double k1, double k2) {
     XCoef c{xc.x, xc.y};
     double g1, g2;
     phase_grad(ph, c, e1, e2, g1, g2);
-    const double r = residual_reduced(ph, c, g1, g2, k1, k2);
     double cs, sn;
-    expi2pi(r, cs, sn);
+    residual_entry(ph, c, g1, g2, k1, k2, cs, sn);
     return make_double2(cs, sn);
 }
 
@@ -244,7 +243,7 @@ __global__ __launch_bounds__(256) void k_gram(Phase ph, const double2 *__restric
             const int col = (which ? tj : ti) * kGramTile + cc;
             double2 v = make_double2(0, 0);
             if (x < x1 && col < r)
-                v = residual_entry(ph, xcoef[x], e1, e2, cols[col].x, cols[col].y);
+                v = residual_at(ph, xcoef[x], e1, e2, cols[col].x, cols[col].y);
             if (which)
                 Aj[rr][cc] = v;
             else
@@ -297,7 +296,7 @@ __global__ void k_gamma_x(Phase ph, const double2 *__restrict__ xcoef, long long
             ar[t] = ai[t] = 0;
         const double2 xc = xcoef[x];
         for (int c = 0; c < r; ++c) {
-            const double2 a = residual_entry(ph, xc, e1, e2, cols[c].x, cols[c].y);
+            const double2 a = residual_at(ph, xc, e1, e2, cols[c].x, cols[c].y);
             const double2 *zr = Z + (long long)c * q + t0;
 #pragma unroll
             for (int t = 0; t < kQ; ++t)
@@ -337,9 +336,8 @@ __global__ void k_gamma_xi(Phase ph, int N, const int *__restrict__ omega, const
         for (int i = 0; i < r; ++i) {
             const double4 rw = rows[i];  // a, b, g1, g2 of row R_i
             XCoef c{rw.x, rw.y};
-            const double ph_r = residual_reduced(ph, c, rw.z, rw.w, k1, k2);
             double cs, sn;
-            expi2pi(ph_r, cs, sn);
+            residual_entry(ph, c, rw.z, rw.w, k1, k2, cs, sn);
 #pragma unroll
             for (int t = 0; t < kQ; ++t)
                 if (t < nt) {
@@ -381,14 +379,15 @@ template __global__ void k_gamma_x<double>(Phase, const double2 *, long long, do
 // ---------------------------------------------------------------------------
 // Host helpers
 // ---------------------------------------------------------------------------
-// Host FP64 residual entry exp(2 pi i Phi_ell(x, xi)) for flat grid index p.
+// Host FP64 residual entry a(x, xi) exp(2 pi i Phi_ell(x, xi)) for flat grid index p.
 zd host_residual(const Phase &ph, int N, long long p, double e1, double e2, double k1, double k2) {
     const double x1 = (double)(p / N) / N, x2 = (double)(p % N) / N;
     XCoef c = phase_xcoef(ph, x1, x2);
     double g1, g2;
     phase_grad(ph, c, e1, e2, g1, g2);
-    const double r = residual_reduced(ph, c, g1, g2, k1, k2);
-    return zd(std::cos(kTwoPi * r), std::sin(kTwoPi * r));
+    double cs, sn;
+    residual_entry(ph, c, g1, g2, k1, k2, cs, sn);
+    return zd(cs, sn);
 }
 
 // k distinct values in [0, n) from the splitmix64 stream `state`.
@@ -991,94 +990,148 @@ static fio_status plan_exact(fio_plan_s *P, const double2 *d_xcoef) {
     return P->precision == FIO_F64 ? store_factors<double>(P, d_xcoef, true) : store_factors<float>(P, d_xcoef, true);
 }
 
-__global__ void k_gather_rows_f32(const cplx<float> *__restrict__ src, const long long *__restrict__ rows, int n,
-                                  int q, double2 *__restrict__ dst) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * q)
-        return;
-    const cplx<float> v = src[rows[i / q] * q + (i % q)];
-    dst[i] = make_double2(v.re, v.im);
-}
-
-// Host copy (FP64) of the stored spatial factors of wedge ell at grid rows `rows`.
-static fio_status fetch_gamma_x(fio_plan_s *P, int l, const std::vector<long long> &rows, std::vector<zd> &out) {
-    const int q = P->wedges[l].qpad, n = (int)rows.size();
-    long long *d_idx = nullptr;
-    double2 *d_out = nullptr;
-    FIO_HIP_TRY(hipMalloc(&d_idx, sizeof(long long) * n));
-    hipError_t e = hipMalloc(&d_out, sizeof(double2) * (size_t)n * q);
+// The network's 16 factors at sampled grid points, FP64 on the host
+// ([i * 16 + t], row-major).
+static fio_status infer_rows(fio_plan_s *P, LearnedModel *net, double theta, const std::vector<long long> &rows,
+                             std::vector<zd> &out) {
+    const int n = (int)rows.size();
+    long long *d_x = nullptr;
+    float *d_y = nullptr;
+    FIO_HIP_TRY(hipMalloc(&d_x, sizeof(long long) * n));
+    hipError_t e = hipMalloc(&d_y, sizeof(float) * (size_t)n * kNetOut);
     if (e == hipSuccess)
-        e = hipMemcpy(d_idx, rows.data(), sizeof(long long) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) {
-        k_gather_rows_f32<<<(n * q + 255) / 256, 256>>>(static_cast<const cplx<float> *>(P->d_gx) + P->wdev[l].gx_off,
-                                                         d_idx, n, q, d_out);
-        e = hipGetLastError();
-    }
-    std::vector<double2> h((size_t)n * q);
+        e = hipMemcpy(d_x, rows.data(), sizeof(long long) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(h.data(), d_out, sizeof(double2) * h.size(), hipMemcpyDeviceToHost);
-    (void)hipFree(d_idx);
-    if (d_out)
-        (void)hipFree(d_out);
+        e = learned_infer_points(net, theta, P->opt.learned_scale, d_x, n, d_y, 0);
+    std::vector<float> h((size_t)n * kNetOut);
+    if (e == hipSuccess)
+        e = hipMemcpy(h.data(), d_y, sizeof(float) * h.size(), hipMemcpyDeviceToHost);
+    (void)hipFree(d_x);
+    if (d_y)
+        (void)hipFree(d_y);
     if (e != hipSuccess)
-        return hip_fail(e, "fetch_gamma_x");
-    out.resize(h.size());
-    for (size_t i = 0; i < h.size(); ++i)
-        out[i] = zd(h[i].x, h[i].y);
+        return hip_fail(e, "learned inference at sampled rows");
+    out.resize((size_t)n * kNetRank);
+    for (size_t i = 0; i < out.size(); ++i)
+        out[i] = zd(h[2 * i], h[2 * i + 1]);
     return FIO_OK;
 }
 
-// Learned factors: gamma^x from the network, gamma^xi refit as
-// alpha_[R]^+ A_[R], and the s x s error estimate of every wedge.  *ok is
-// false if any wedge misses the separation target.
+// Learned factors.  For each wedge the network gives alpha_t (t < 16) at the
+// sampled rows R and at the rows Gamma of the s x s estimate (Section 4);
+// gamma^xi is the least-squares refit alpha_[R]^+ A_[R] of the leading q
+// factors, and q is the smallest rank whose estimate meets the separation
+// target (the factors are ordered by the singular values of their targets,
+// so the leading ones carry the most energy).  Only then are the q factors
+// inferred on the whole grid and stored, at the plan's padded rank, so the
+// apply runs at the rank the tolerance needs.  *ok is false if even the 16
+// factors miss the target on some wedge.
 static fio_status plan_learned(fio_plan_s *P, LearnedModel *net, const double2 *d_xcoef, bool *ok) {
     *ok = true;
-    const long long NN = (long long)P->N * P->N;
-    for (WedgeHost &W : P->wedges)
-        W.q = W.members.empty() ? 0 : kNetRank;
-    fio_status st = plan_layout(P);
-    if (st != FIO_OK)
-        return st;
+    const int N = P->N, h = N / 2;
+    const long long NN = (long long)N * N;
     P->factor_mode = FIO_FACTORS_LEARNED;
     const double target = 0.5 * P->tol;
     const int sv = std::max(8, P->opt.verify_samples);
     const int rr = std::max(4 * kNetRank, std::min(512, std::max(P->opt.r0, 8 * kNetRank)));
     for (int l = 0; l < P->L; ++l) {
         WedgeHost &W = P->wedges[l];
-        if (W.q == 0)
-            continue;
-        FIO_HIP_TRY(learned_infer_wedge(net, W.theta, P->opt.learned_scale,
-                                        static_cast<cplx<float> *>(P->d_gx) + P->wdev[l].gx_off, W.qpad, P->precision,
-                                        0));
-    }
-    FIO_HIP_TRY(hipDeviceSynchronize());
-    for (int l = 0; l < P->L; ++l) {
-        WedgeHost &W = P->wedges[l];
-        if (W.q == 0)
+        W.q = 0;
+        if (W.members.empty())
             continue;
         uint64_t state = splitmix64(P->opt.seed ^ (0x1EA2Dull * (uint64_t)(l + 1)));
         W.R = sample_distinct<long long>(NN, (int)std::min<long long>(rr, NN), state);
         W.C.clear();
         W.Z.clear();
         W.r = (int)W.R.size();
-        std::vector<zd> aR;
-        st = fetch_gamma_x(P, l, W.R, aR);
-        if (st != FIO_OK)
-            return st;
-        pinv_tall((int)W.R.size(), W.q, aR, W.P, 1e-6);
-        const int nmem = (int)W.members.size();
+        const int nmem = (int)W.members.size(), nr = W.r;
         const int sg = (int)std::min<long long>(sv, NN), sd = std::min(sv, nmem);
         std::vector<long long> Gam = sample_distinct<long long>(NN, sg, state);
         std::vector<int> Del = sample_distinct<int>(nmem, sd, state);
-        std::vector<zd> UG;
-        st = fetch_gamma_x(P, l, Gam, UG);
+        std::vector<zd> aR, aG;
+        fio_status st = infer_rows(P, net, W.theta, W.R, aR);
+        if (st == FIO_OK)
+            st = infer_rows(P, net, W.theta, Gam, aG);
         if (st != FIO_OK)
             return st;
-        W.sep_err = separation_estimate(P, W, Gam, Del, UG);
-        P->learned_sep_err = std::max(P->learned_sep_err, W.sep_err);
-        if (W.sep_err > target)
+        // residual kernel at (R, Delta) and (Gamma, Delta), once for every trial rank
+        const double e1 = std::cos(W.theta), e2 = std::sin(W.theta);
+        std::vector<zd> ARD((size_t)nr * sd), AGD((size_t)sg * sd);
+        double den = 0;
+        for (int j = 0; j < sd; ++j) {
+            const int om = W.members[Del[j]];
+            const double k1 = om / N - h, k2 = om % N - h;
+            for (int i = 0; i < nr; ++i)
+                ARD[(size_t)i * sd + j] = host_residual(P->phase, N, W.R[i], e1, e2, k1, k2);
+            for (int i = 0; i < sg; ++i) {
+                AGD[(size_t)i * sd + j] = host_residual(P->phase, N, Gam[i], e1, e2, k1, k2);
+                den += std::norm(AGD[(size_t)i * sd + j]);
+            }
+        }
+        // estimate of the rank-q refit; Pq = alpha_[R](:, :q)^+
+        auto estimate = [&](int q, std::vector<zd> &Pq) {
+            std::vector<zd> U((size_t)nr * q);
+            for (int i = 0; i < nr; ++i)
+                for (int t = 0; t < q; ++t)
+                    U[(size_t)i * q + t] = aR[(size_t)i * kNetRank + t];
+            pinv_tall(nr, q, U, Pq, 1e-6);
+            std::vector<zd> TD((size_t)q * sd, zd(0, 0));
+            for (int t = 0; t < q; ++t)
+                for (int i = 0; i < nr; ++i) {
+                    const zd pv = Pq[(size_t)t * nr + i];
+                    const zd *arow = &ARD[(size_t)i * sd];
+                    zd *trow = &TD[(size_t)t * sd];
+                    for (int j = 0; j < sd; ++j)
+                        trow[j] += pv * arow[j];
+                }
+            double num = 0;
+            for (int i = 0; i < sg; ++i)
+                for (int j = 0; j < sd; ++j) {
+                    zd v(0, 0);
+                    for (int t = 0; t < q; ++t)
+                        v += aG[(size_t)i * kNetRank + t] * TD[(size_t)t * sd + j];
+                    num += std::norm(AGD[(size_t)i * sd + j] - v);
+                }
+            return std::sqrt(num / std::max(den, 1e-300));
+        };
+        std::vector<zd> Pq;
+        double err = estimate(kNetRank, Pq);
+        int q = kNetRank;
+        if (err > target) {
             *ok = false;
+        } else {
+            // smallest rank meeting the target; the error falls with the rank
+            int lo = 1, hi = kNetRank;
+            while (lo < hi) {
+                const int mid = (lo + hi) / 2;
+                std::vector<zd> Pm;
+                if (estimate(mid, Pm) <= target)
+                    hi = mid;
+                else
+                    lo = mid + 1;
+            }
+            q = lo;
+            err = estimate(q, Pq);
+        }
+        W.q = q;
+        W.P = Pq;
+        W.sep_err = err;
+        P->learned_sep_err = std::max(P->learned_sep_err, err);
     }
+    if (!*ok)
+        return FIO_OK;
+    fio_status st = plan_layout(P);
+    if (st != FIO_OK)
+        return st;
+    for (int l = 0; l < P->L; ++l) {
+        WedgeHost &W = P->wedges[l];
+        if (W.q == 0)
+            continue;
+        FIO_HIP_TRY(learned_infer_wedge(net, W.theta, P->opt.learned_scale,
+                                        static_cast<cplx<float> *>(P->d_gx) + P->wdev[l].gx_off, W.q, W.qpad,
+                                        P->precision, 0));
+    }
+    FIO_HIP_TRY(hipDeviceSynchronize());
     return store_factors<float>(P, d_xcoef, false);
 }
 
@@ -1095,7 +1148,7 @@ static fio_status plan_learned(fio_plan_s *P, LearnedModel *net, const double2 *
 // ---------------------------------------------------------------------------
 namespace {
 constexpr char kPlanMagic[8] = {'F', 'I', 'O', 'P', 'L', 'A', 'N', '1'};
-constexpr uint32_t kPlanVersion = 1;
+constexpr uint32_t kPlanVersion = 2;  // 2: the amplitude kind follows the phase kind
 
 struct PlanWriter {
     FILE *f;
@@ -1175,6 +1228,7 @@ fio_status save_plan(const fio_plan_s *P, const char *path) {
     w.put<uint32_t>(kPlanVersion);
     w.put<int32_t>(P->N);
     w.put<int32_t>(P->phase.kind);
+    w.put<int32_t>(P->phase.amp);
     for (double v : P->phase.p)
         w.put<double>(v);
     w.put<double>(P->tol);
@@ -1235,6 +1289,9 @@ fio_status load_plan(fio_plan_s *P, const char *path) {
     const int N = r.get<int32_t>();
     Phase ph{};
     ph.kind = r.get<int32_t>();
+    ph.amp = r.get<int32_t>();
+    if (ph.amp != 0 && ph.amp != 1)
+        return bad("unknown amplitude kind");
     for (double &v : ph.p)
         v = r.get<double>();
     const double tol = r.get<double>();
@@ -1382,10 +1439,10 @@ fio_status build_plan(fio_plan_s *P) {
         net && (P->opt.factor_mode == FIO_FACTORS_AUTO || P->opt.factor_mode == FIO_FACTORS_LEARNED);
     bool use_net = want_net;
     if (want_net && (net->N != N || net->L != P->L || P->opt.partition != FIO_PART_EQUIANGULAR ||
-                     P->precision != FIO_F32 || net->family.kind != P->phase.kind)) {
+                     P->precision != FIO_F32 || net->family.kind != P->phase.kind || P->phase.amp != 0)) {
         if (P->opt.factor_mode == FIO_FACTORS_LEARNED)
-            return (set_error("the network was trained for another N, wedge count, partition, precision or "
-                              "phase family"),
+            return (set_error("the network was trained for another N, wedge count, partition, precision, "
+                              "phase family or amplitude"),
                     FIO_EINVAL);
         use_net = false;
     }

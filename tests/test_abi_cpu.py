@@ -143,6 +143,11 @@ def test_plan_files_are_checked_before_device_use(lib, tmp_path):
     assert b"not a plan file" in lib.fio_last_error()
     # the right magic and version, then a header cut short
     cut = tmp_path / "cut.plan"
-    cut.write_bytes(b"FIOPLAN1" + (1).to_bytes(4, "little") + (128).to_bytes(4, "little"))
+    cut.write_bytes(b"FIOPLAN1" + (2).to_bytes(4, "little") + (128).to_bytes(4, "little"))
     assert lib.fio_plan_load(str(cut).encode(), ctypes.byref(h)) == fio.FIO_EINVAL
     assert not h.value
+    # a file of the first format (no amplitude field) is refused by its version
+    old = tmp_path / "old.plan"
+    old.write_bytes(b"FIOPLAN1" + (1).to_bytes(4, "little") + bytes(64))
+    assert lib.fio_plan_load(str(old).encode(), ctypes.byref(h)) == fio.FIO_EINVAL
+    assert b"version" in lib.fio_last_error()
