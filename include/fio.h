@@ -73,8 +73,16 @@ typedef struct {
     double p[8];
 } fio_phase;
 
-/* Amplitude a(x, xi).  Only a = 1 (Egorov form) is supported; other kinds give FIO_ENOTSUP. */
-enum { FIO_AMP_ONE = 0 };
+/* Amplitude a(x, xi).  FIO_AMP_ONE: a = 1 (the Egorov form, Section 3).
+ * FIO_AMP_BESSEL: the amplitude of the integration along ellipses (Section 4,
+ * eq. (ellipses_amp), '+' sign), a = (1/4pi)(J0(2 pi rho) + i Y0(2 pi rho))
+ * exp(-2 pi i rho) with rho = h(x, xi), for phases with h >= 0 (kinds 1-5 with
+ * p0 >= 0, and |p1| <= 1 for kind 3; FIO_EINVAL otherwise); a(x, 0) = 0, since
+ * Y0 is singular at 0 and the paper states no value there.  The amplitude is
+ * folded into the separated kernel a exp(2 pi i Phi_ell) of every wedge, as
+ * Section 4 describes.  Plans with FIO_AMP_BESSEL do not use a learned
+ * network.  Other kinds give FIO_ENOTSUP. */
+enum { FIO_AMP_ONE = 0, FIO_AMP_BESSEL = 1 };
 typedef struct {
     int kind;
     double p[4];
@@ -169,6 +177,21 @@ fio_status fio_apply(fio_plan_t plan, const void *fhat, void *u, void *stream);
 /* B right-hand sides, fhat and u holding B arrays each; the factors, warped
  * points and kernel weights are shared across the batch. */
 fio_status fio_apply_batch(fio_plan_t plan, int B, const void *fhat, void *u, void *stream);
+
+/* The adjoint (Section 3.5): the Fourier coefficients of L*g,
+ *     hhat(xi) = (1/N) sum_{y in X} conj(a(y, xi)) exp(-2 pi i Phi(y, xi)) g(y),  xi in Omega,
+ * for g on the grid X (row-major, like u) and hhat centred (like fhat): the
+ * conjugate transpose of the map fio_apply computes, so that
+ * <L fhat, g> = <fhat, L* g>.  It runs the algorithm of Section 3.5 with the
+ * plan's wedges, separated factors, grids and kernel (type-1 NUFFT: spreading
+ * of conj(gamma^x) g onto each wedge's oversampled grid, the transposed FFT
+ * stages, and the sum over ranks with conj(gamma^xi)); the computed map is the
+ * exact adjoint of the computed forward map up to rounding.  An inverse 2-D
+ * DFT of hhat gives (L*g)(x).  It uses the plan's workspace, so a plan runs
+ * one forward or adjoint apply at a time.  B right-hand sides are back to
+ * back, as in fio_apply_batch. */
+fio_status fio_apply_adjoint(fio_plan_t plan, const void *g, void *hhat, void *stream);
+fio_status fio_apply_adjoint_batch(fio_plan_t plan, int B, const void *g, void *hhat, void *stream);
 
 /* fio_apply_batch for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation).

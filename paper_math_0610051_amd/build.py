@@ -19,7 +19,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 OBJ_DIR = os.path.join(OUT_DIR, "obj")
 LIB_PATH = os.path.join(OUT_DIR, "libfio.so")
 
-HIP_SOURCES = ["abi.hip", "plan.hip", "apply.hip", "multi.hip", "learned.hip", "autotune.hip"]
+HIP_SOURCES = ["abi.hip", "plan.hip", "apply.hip", "adjoint.hip", "multi.hip", "learned.hip", "autotune.hip"]
 CXX_SOURCES = ["linalg.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 
+#include "adjoint.hpp"
 #include "apply.hpp"
 #include "errors.hpp"
 #include "linalg.hpp"
@@ -120,8 +121,18 @@ fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, 
         return (set_error("N must be even and in [8, 4096]"), FIO_EINVAL);
     if (phase->kind < 0 || phase->kind > 5)
         return (set_error("unknown phase kind"), FIO_EINVAL);
-    if (amp && amp->kind != FIO_AMP_ONE)
-        return (set_error("only the amplitude a = 1 is supported"), FIO_ENOTSUP);
+    const int ak = amp ? amp->kind : FIO_AMP_ONE;
+    if (ak != FIO_AMP_ONE && ak != FIO_AMP_BESSEL)
+        return (set_error("unknown amplitude kind"), FIO_ENOTSUP);
+    if (ak == FIO_AMP_BESSEL) {
+        // rho = h(x, xi) must be nonnegative
+        const double *pp = phase->p;
+        const bool nonneg = (phase->kind == 1 && pp[0] >= 0) || (phase->kind == 2 && pp[0] >= 0) ||
+                            (phase->kind == 3 && pp[0] >= 0 && std::fabs(pp[1]) <= 1) ||
+                            (phase->kind == 4 && pp[0] >= 0) || (phase->kind == 5 && pp[0] >= 0);
+        if (!nonneg)
+            return (set_error("the Bessel amplitude needs a phase with h(x, xi) >= 0"), FIO_EINVAL);
+    }
     if (!(tol > 0 && tol < 1))
         return (set_error("tol must lie in (0, 1)"), FIO_EINVAL);
     fio_options o;
@@ -153,6 +164,7 @@ fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, 
     P->serial = next_plan_serial();
     P->N = N;
     P->phase.kind = phase->kind;
+    P->phase.amp = ak;
     std::memcpy(P->phase.p, phase->p, sizeof(P->phase.p));
     P->tol = tol;
     P->opt = o;
@@ -264,6 +276,23 @@ fio_status fio_apply_batch_noalloc(fio_plan_t P, int B, const void *fhat, void *
         return hip_fail(ds.err, "hipSetDevice");
     FIO_HIP_TRY(apply_launch_scratch(P, B, fhat, u, static_cast<hipStream_t>(stream)));
     return FIO_OK;
+}
+
+fio_status fio_apply_adjoint_batch(fio_plan_t P, int B, const void *g, void *hhat, void *stream) {
+    set_error("");
+    if (!P || !g || !hhat)
+        return (set_error("null argument"), FIO_EINVAL);
+    if (B < 1)
+        return (set_error("B must be >= 1"), FIO_EINVAL);
+    DeviceScope ds(P->device);
+    if (ds.err != hipSuccess)
+        return hip_fail(ds.err, "hipSetDevice");
+    FIO_HIP_TRY(adjoint_launch(P, B, g, hhat, static_cast<hipStream_t>(stream)));
+    return FIO_OK;
+}
+
+fio_status fio_apply_adjoint(fio_plan_t plan, const void *g, void *hhat, void *stream) {
+    return fio_apply_adjoint_batch(plan, 1, g, hhat, stream);
 }
 
 fio_status fio_apply_wedges(fio_plan_t plan, int l0, int l1, int B, const void *fhat, void *u, void *stream) {

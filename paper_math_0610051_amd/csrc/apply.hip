@@ -19,6 +19,7 @@
 #include <mutex>
 
 #include "apply.hpp"
+#include "interp_util.hpp"
 
 namespace fio {
 
@@ -289,17 +290,6 @@ __global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(kFf
     cols_body<T>(I.a, m.it, m.b);
 }
 
-template <typename T>
-__device__ inline void expi_t(double r, T &c, T &s);
-template <>
-__device__ inline void expi_t<float>(double r, float &c, float &s) {
-    expi2pi_f((float)r, c, s);
-}
-template <>
-__device__ inline void expi_t<double>(double r, double &c, double &s) {
-    expi2pi(r, c, s);
-}
-
 // ---------------------------------------------------------------------------
 // Stage 3: interpolate + modulate + combine over t + accumulate over ell.
 // A workgroup owns a kTileX x kTileX tile of output points (one per thread)
@@ -324,41 +314,6 @@ struct Unit16<double> {
     using type = double2;
 };
 
-__device__ inline int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = min(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ inline int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = max(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ inline double wave_min(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = fmin(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ inline double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = fmax(v, __shfl_xor(v, o));
-    return v;
-}
-
-// Grid coordinate u = m (y - k) and the first cell floor(u - w/2) + 1 of the
-// stencil, without floating-point contraction, so that every thread and the
-// window bounds map equal inputs to equal results; the map is monotone in y.
-template <int W>
-__device__ inline int stencil_origin(double m, double y, double k, double &u) {
-#pragma clang fp contract(off)
-    u = m * (y - k);
-    return (int)floor(u - 0.5 * W) + 1;
-}
-
 // Row stride (16-byte units) of the staged window.  A ds_read_b128 serves 16
 // lanes of a wave per cycle from 64 four-byte banks, i.e. 16 unit residues:
 // two different cells whose unit addresses agree mod 16 cost an extra cycle,
@@ -373,22 +328,6 @@ __device__ inline int stencil_origin(double m, double y, double k, double &u) {
 // the number of distinct residues, summed over the workgroup; the lowest
 // score wins, ties going to the smaller stride.  Lane sets whose cells spread
 // beyond 16 x 4 are not scored.  Contains one block barrier.
-// Kernel weight phi(z) = exp(beta (sqrt(1 - (2z/w)^2) - 1)) of the ES kernel.
-// In FP32 the hardware base-2 exponential and square root suffice: the
-// argument of the exponential lies in [-beta log2(e), 0] and 1 - (2z/w)^2 is
-// either at most 0 or at least 2^-23, so neither needs the range and
-// denormal handling of the library functions; their error (about one ulp)
-// is below that of the FP32 argument itself.
-template <typename T>
-__device__ __forceinline__ T es_weight(T z, T two_over_w, T beta) {
-    if constexpr (sizeof(T) == 4) {
-        const float u = z * two_over_w, s = 1.0f - u * u;
-        return s > 0.0f ? __builtin_amdgcn_exp2f(beta * 1.44269504f * (__builtin_amdgcn_sqrtf(s) - 1.0f)) : 0.0f;
-    } else {
-        return es_kernel<T>(z, two_over_w, beta);
-    }
-}
-
 constexpr int kPassXor[4] = {1, 2, 12, 24};  // generators of one ds_read_b128 lane set
 __device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int lane, int wave,
                                       unsigned long long *red2) {
@@ -526,7 +465,7 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                 for (int cc = 0; cc < wd.zrc; ++cc) {
                     const double2 k = zc[cc];
                     double cs2, sn2;
-                    expi2pi(residual_reduced(a.phase, c, g1, g2, k.x, k.y), cs2, sn2);
+                    residual_entry(a.phase, c, g1, g2, k.x, k.y, cs2, sn2);
                     const double2 *zr = zm + (long long)cc * q + t0;
 #pragma unroll
                     for (int t = 0; t < kC; ++t)
@@ -881,6 +820,9 @@ PlanArgs<T> make_args(const fio_plan_s *P) {
     a.zmat = static_cast<const double2 *>(P->d_zmat);
     return a;
 }
+
+template PlanArgs<float> make_args<float>(const fio_plan_s *P);
+template PlanArgs<double> make_args<double>(const fio_plan_s *P);
 
 // Dynamic LDS of the interpolation: the window buffers, plus gamma^x of the
 // tile's points (kThreads x qmax complex; regenerated in FIO_FACTORS_REGEN,

@@ -98,6 +98,9 @@ size_t inst_args_size(int precision);
 void fill_inst_args(const fio_plan_s *P, const void *fhat, void *u, int B, void *out);
 
 hipError_t apply_prepare(fio_plan_s *P);
+// Kernel-side view of a plan (instantiated for float and double).
+template <typename T>
+PlanArgs<T> make_args(const fio_plan_s *P);
 // Zero `bytes` (a multiple of 8) with a fill kernel on stream s (no memset node).
 hipError_t zero_fill(void *ptr, size_t bytes, hipStream_t s);
 hipError_t apply_launch(fio_plan_s *P, int B, const void *fhat, void *u, hipStream_t s, int l0, int l1);

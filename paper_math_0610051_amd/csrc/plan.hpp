@@ -130,6 +130,7 @@ struct fio_plan_s {
     // rows of the row/column work tables restricted to a wedge range are
     // found by scanning: rows and cols are sorted by wedge.
     std::vector<int> row_first, col_first;   // L+1 prefix offsets
+    bool adjoint_ready = false;  // LDS limits of the adjoint kernels set
     // optional per-stage event timing
     int profiling = 0;
     struct StageEvents {

@@ -89,6 +89,8 @@ def load_library():
         "fio_apply_multi": (c_int, [c_int, POINTER(P), POINTER(P), POINTER(P), POINTER(c_int), P]),
         "fio_apply_wedges": (c_int, [P, c_int, c_int, c_int, P, P, P]),
         "fio_apply_batch_noalloc": (c_int, [P, c_int, P, P, P]),
+        "fio_apply_adjoint": (c_int, [P, P, P, P]),
+        "fio_apply_adjoint_batch": (c_int, [P, c_int, P, P, P]),
         "fio_plan_info": (c_int, [P, POINTER(fio_plan_info_t)]),
         "fio_wedge_info": (c_int, [P, c_int, POINTER(fio_wedge_info_t)]),
         "fio_wedge_map": (c_int, [P, P]),
@@ -165,18 +167,23 @@ def _torch():
     return torch
 
 
+AMPLITUDES = {"one": 0, "bessel": 1}
+
+
 class Plan:
-    """A built operator: fio_plan_ex(N, phase, a = 1, tol, options)."""
+    """A built operator: fio_plan_ex(N, phase, amplitude, tol, options); amplitude
+    "one" (a = 1) or "bessel" (the Section 4 amplitude)."""
 
     def __init__(self, N, phase, tol, *, params=(), precision="f32", partition="equiangular", n_wedges=0,
                  seed=None, max_batch=8, sep_tol_frac=None, nufft_tol_frac=None, sigma=None, kernel_width=0,
-                 r0=0, verify_samples=0, factor_mode="auto", learned=None, learned_scale=1.0):
+                 r0=0, verify_samples=0, factor_mode="auto", learned=None, learned_scale=1.0, amplitude="one"):
         lib = load_library()
         self._lib = lib
         self.N = int(N)
         self.precision = precision
         ph = phase if isinstance(phase, fio_phase) else make_phase(phase, params)
         amp = fio_amplitude()
+        amp.kind = AMPLITUDES[amplitude]
         o = default_options()
         o.precision = PRECISIONS[precision]
         o.partition = PARTITIONS[partition]
@@ -273,6 +280,13 @@ class Plan:
         fhat, out, B, stream = self._io(fhat, out)
         _check(self._lib.fio_apply_batch(self.handle, B, c_void_p(fhat.data_ptr()), c_void_p(out.data_ptr()),
                                          c_void_p(stream)))
+        return out
+
+    def apply_adjoint(self, g, out=None):
+        """Fourier coefficients of L*g (centred) for (N, N) or (B, N, N) row-major g."""
+        g, out, B, stream = self._io(g, out)
+        _check(self._lib.fio_apply_adjoint_batch(self.handle, B, c_void_p(g.data_ptr()), c_void_p(out.data_ptr()),
+                                                 c_void_p(stream)))
         return out
 
     def apply_noalloc(self, fhat, out):

@@ -19,7 +19,7 @@ import json
 import os
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-KERNEL_SOURCES = ("apply.hip", "apply.hpp", "common.hpp", "fft.hpp", "plan.hpp")
+KERNEL_SOURCES = ("apply.hip", "apply.hpp", "common.hpp", "fft.hpp", "interp_util.hpp", "plan.hpp")
 
 
 def _code_only(text: str) -> str:

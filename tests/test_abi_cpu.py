@@ -93,7 +93,8 @@ def _plan_status(N=64, kind=2, tol=1e-4, amp_kind=0, **opts):
     (dict(kind=9), fio.FIO_EINVAL),
     (dict(tol=0.0), fio.FIO_EINVAL),
     (dict(tol=1.5), fio.FIO_EINVAL),
-    (dict(amp_kind=1), fio.FIO_ENOTSUP),
+    (dict(amp_kind=2), fio.FIO_ENOTSUP),
+    (dict(amp_kind=1, kind=0), fio.FIO_EINVAL),   # the Bessel amplitude needs h >= 0
     (dict(tol=1e-8), fio.FIO_ENOTSUP),
     (dict(tol=3e-7, precision=1), fio.FIO_ENOTSUP),
     (dict(precision=7), fio.FIO_EINVAL),
