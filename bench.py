@@ -12,6 +12,7 @@ Other workloads (each prints its own JSON line):
   --workload batch512 64 right-hand sides at N = 512 in one fused graph launch
   --workload uneven   32 instances, N in {128, ..., 1024}, one fused launch
   --workload learned  network-factor plan vs exact plan at N = 1024
+  --workload paper    the paper's Table 3 / Table 4 examples, N = 64 ... 512
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched]
 """
@@ -430,6 +431,7 @@ def run_learned(args):
                              learned_applies_per_s=B * n / el, exact_applies_per_s=B * n / ee,
                              learned_err=err_l, exact_err=err_e, learned_attempt_sep_err=il["learned_sep_error"],
                              learned_attempt_ms=il["learned_ms"], plan_max_sep_err=il["max_sep_error"],
+                             learned_ranks=[il["min_rank"], il["max_rank"]], exact_ranks=[ie["min_rank"], ie["max_rank"]],
                              learned_factor_bytes=il["factor_bytes"], exact_compressed_bytes=ie["compressed_bytes"]))
             pl.close()
             pe.close()
@@ -442,12 +444,70 @@ def run_learned(args):
     print(json.dumps(res), flush=True)
 
 
+# The paper's Tables 3 and 4 (Matlab, one 2.6 GHz CPU): N -> (eps, preprocessing s, evaluation s, error, MB).
+PAPER_TABLE3 = {64: (2.44e-3, 2.06, 3.89, 2.08e-3, 0.76), 128: (6.10e-4, 10.9, 24.5, 8.02e-4, 1.26),
+                256: (1.53e-4, 81.0, 165.0, 1.00e-4, 2.01), 512: (3.81e-5, 467.0, 988.0, 4.22e-5, 3.06)}
+PAPER_TABLE4 = {64: (2.44e-3, 21.8, 36.7, 7.30e-4, 0.37), 128: (6.10e-4, 109.0, 165.0, 4.00e-4, 0.59),
+                256: (1.53e-4, 662.0, 846.0, 1.39e-4, 0.89), 512: (3.81e-5, 3420.0, 4430.0, 3.69e-5, 1.38)}
+
+
+def run_paper(args):
+    """The paper's own examples at eps = 10 N^-2: the ellipse phase of eq.
+    (nrphase) (Table 3) and the circles of eq. (circlerad) with the Bessel
+    amplitude of eq. (ellipses_amp) (Table 4), white-noise f, N = 64 ... 512;
+    per row: plan and apply time, applies/s, ranks, factor storage and the
+    relative l2 error against the FP64 direct sum at 512 sampled outputs (the
+    paper used 100), beside the paper's own figures (context only)."""
+    import numpy as np
+    import torch
+
+    import fio_inputs as fi
+    from oracle import direct as od
+    from paper_math_0610051_amd import Plan
+
+    od.build(force=False)
+    rows = []
+    for table, kind, amp, paper in (("3", 4, 0, PAPER_TABLE3), ("4", 5, 1, PAPER_TABLE4)):
+        for N in (64, 128, 256, 512):
+            eps = 10.0 / N ** 2
+            rng = fi.rng_for(6, N + amp)
+            fh = fi.fhat_from_f(fi.white_noise_real(N, rng))
+            fd = torch.from_numpy(fh.astype(np.complex64)).cuda()
+            t0 = time.perf_counter()
+            plan = Plan(N, kind, eps, params=(1.0,), amplitude="bessel" if amp else "one")
+            plan_s = time.perf_counter() - t0
+            out = torch.empty_like(fd)
+            el = time_applies(plan, fd, out, args.steps, args.warmup)
+            xs = fi.sample_points(N, 512, rng)
+            got = out.cpu().numpy().astype(np.complex128).ravel()[xs]
+            exact = od.direct(N, kind, (1.0,), fh, xs, amp=amp)
+            err = float(np.linalg.norm(got - exact) / np.linalg.norm(exact))
+            info = plan.info()
+            pe = paper[N]
+            rows.append(dict(table=table, N=N, eps=eps, rel_l2=err, meets_eps=err <= eps, plan_s=plan_s,
+                             apply_s=el / args.steps, applies_per_s=args.steps / el, L=info["L"],
+                             ranks=[info["min_rank"], info["max_rank"]], kernel_width=info["kernel_width"],
+                             factor_mb=info["factor_bytes"] / 1e6, compressed_mb=info["compressed_bytes"] / 1e6,
+                             paper=dict(eps=pe[0], preprocessing_s=pe[1], evaluation_s=pe[2], error=pe[3],
+                                        storage_mb=pe[4])))
+            log("table %s N=%d: err %.2e (eps %.2e), apply %.3f ms, ranks %d..%d"
+                % (table, N, err, eps, 1e3 * el / args.steps, info["min_rank"], info["max_rank"]))
+            plan.close()
+    res = dict(metric="the paper's Table 3 / Table 4 examples at eps = 10 N^-2 (applies/s and error per N)",
+               value=None, unit="applies/s", n_gpus=1, steps=args.steps, warmup=args.warmup, higher_is_better=True,
+               dtype="c64 (fp32 data, fp64 phase, points and amplitude)", data="synthetic white noise",
+               config=dict(workload="paper examples: ellipse phase (Table 3), circles with Bessel amplitude "
+                                    "(Table 4), N = 64 ... 512"),
+               rows=rows, roofline=None, cpu_baseline=None, vs_baseline=None)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("batched", "batch512", "uneven", "learned"), default="batched")
+    ap.add_argument("--workload", choices=("batched", "batch512", "uneven", "learned", "paper"), default="batched")
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-4)
@@ -471,7 +531,7 @@ def main():
               "with one sum of the partial outputs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     {"batched": run_batched, "batch512": run_batch512, "uneven": run_uneven,
-     "learned": run_learned}[args.workload](args)
+     "learned": run_learned, "paper": run_paper}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -104,7 +104,10 @@ typedef struct {
     int precision;          /* FIO_F32 (default): FP32 data, FFT and combine, FP64 phase and points;
                                FIO_F64: FP64 throughout */
     int partition;          /* FIO_PART_EQUIANGULAR (Section 1.3) or FIO_PART_CORONAE (dyadic rings) */
-    int n_wedges;           /* equiangular wedge count L; 0 = 8 * ceil(sqrt(N) / 8) */
+    int n_wedges;           /* equiangular wedge count L; 0 = automatic: the network's L when a learned
+                               network of the same N is given, else L ~ sqrt(N) (Section 1.3) raised for
+                               strong phases: the multiple of 8 at least 8 ceil(sqrt(N) / 8) and
+                               pi sqrt(S N / (1.5 sqrt 2)), S = max |grad_xi h| of the family */
     int factor_mode;        /* FIO_FACTORS_AUTO / STORED / REGEN (exact separation) / LEARNED (network) */
     unsigned long long seed;/* seed of the column/row sampling of the separation */
     int max_batch;          /* right-hand sides processed per pass of the workspace (default 8) */
@@ -254,8 +257,9 @@ const char *fio_last_error(void);
 
 /* Host linear algebra of the plan, exported for CPU tests (no device use):
  * Hermitian eigen-decomposition of an n x n complex double matrix (row-major,
- * interleaved) by cyclic Jacobi; w: n eigenvalues in descending order, V:
- * n x n eigenvectors as columns (row-major). */
+ * interleaved) by Householder tridiagonalisation and implicit QL; w: n
+ * eigenvalues in descending order, V: n x n eigenvectors as columns
+ * (row-major). */
 fio_status fio_host_eigh(int n, const double *A, double *w, double *V);
 
 /* Relative l2 error (the Section 4 estimator) of a computed u = L fhat at

@@ -566,7 +566,7 @@ fio_status fio_host_eigh(int n, const double *A, double *w, double *V) {
     for (size_t i = 0; i < M.size(); ++i)
         M[i] = zd(A[2 * i], A[2 * i + 1]);
     std::vector<double> lam;
-    eigh_jacobi(n, M, lam, Vec);
+    eigh(n, M, lam, Vec);
     for (int i = 0; i < n; ++i)
         w[i] = lam[i];
     for (size_t i = 0; i < Vec.size(); ++i) {

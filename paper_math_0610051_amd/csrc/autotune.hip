@@ -246,7 +246,10 @@ fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp,
         *ntried = 0;
     if (cache_lookup(cache, key, best))
         return FIO_OK;
-    const int L0 = o.n_wedges > 0 ? o.n_wedges : 8 * (int)std::ceil(std::sqrt((double)N) / 8.0);
+    Phase ph0{};
+    ph0.kind = phase->kind;
+    std::memcpy(ph0.p, phase->p, sizeof(ph0.p));
+    const int L0 = o.n_wedges > 0 ? o.n_wedges : default_wedge_count(N, ph0);
     // fewer wedges rarely pay at large N, where ranks grow fastest with the angular width
     std::vector<int> Ls;
     if (N <= 256)

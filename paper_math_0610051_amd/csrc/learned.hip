@@ -586,9 +586,9 @@ fio_status fio_learned_create(int N, const fio_phase *family, int n_wedges, unsi
     if (!M)
         return (set_error("host allocation failed"), FIO_ENOMEM);
     M->N = N;
-    M->L = n_wedges > 0 ? n_wedges : 8 * (int)std::ceil(std::sqrt((double)N) / 8.0);
     M->family.kind = family->kind;
     std::memcpy(M->family.p, family->p, sizeof(M->family.p));
+    M->L = n_wedges > 0 ? n_wedges : default_wedge_count(N, M->family);
     M->seed = seed;
     fio_status st = init_model(M);
     if (st != FIO_OK) {
@@ -699,7 +699,7 @@ fio_status fio_learned_generate(fio_learned_t m, int nscales, const double *scal
         }
         std::vector<double> lam;
         std::vector<zd> Vr;
-        eigh_jacobi(r, Gsum, lam, Vr);
+        eigh(r, Gsum, lam, Vr);
         m->s1[l] = std::sqrt(std::max(lam[0], 1e-300) / nscales);
         m->V[l].assign((size_t)r * kNetRank, zd(0, 0));
         for (int c = 0; c < r; ++c)

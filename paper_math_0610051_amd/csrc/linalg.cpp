@@ -7,72 +7,148 @@
 
 namespace fio {
 
-// Cyclic Jacobi for a complex Hermitian matrix.  Each rotation acts on the
-// pair (p, q) with a_pq = |a_pq| e^{i phi}:
-//   J = [[c, s e^{i phi}], [-s e^{-i phi}, c]],  A <- J^H A J,  V <- V J,
-// with t = s / c the smaller root of t^2 + 2 tau t - 1 = 0,
-// tau = (a_qq - a_pp) / (2 |a_pq|), which zeroes the (p, q) entry.
-int eigh_jacobi(int n, std::vector<zd> &A, std::vector<double> &w, std::vector<zd> &V) {
+// Householder tridiagonalisation and implicit QL (Golub and Van Loan,
+// "Matrix Computations", Sections 8.3.1 and 8.3.5).
+//  1. For k = 0 .. n-3 a reflector H_k = I - 2 v v^H (|v| = 1, v zero in
+//     rows 0..k) maps column k below the diagonal onto a multiple of e_{k+1};
+//     A <- H_k A H_k is applied as A - v w^H - w v^H with p = 2 A v,
+//     w = p - (v^H p) v, and Q <- Q H_k accumulates the reflectors.
+//  2. The Hermitian tridiagonal result has complex off-diagonals b_k; the
+//     unitary diagonal D with D_{k+1} = D_k b_k / |b_k| turns it into the
+//     real symmetric tridiagonal T = D^H (Q^H A Q) D with off-diagonal |b_k|.
+//  3. Implicit QL with Wilkinson shifts diagonalises T by plane rotations,
+//     applied to the columns of Z = Q D, which then hold the eigenvectors.
+int eigh(int n, std::vector<zd> &A, std::vector<double> &w, std::vector<zd> &V) {
+    auto at = [&](int i, int j) -> zd & { return A[(size_t)i * n + j]; };
+    std::vector<zd> Q((size_t)n * n, zd(0, 0));
+    for (int i = 0; i < n; ++i)
+        Q[(size_t)i * n + i] = 1.0;
+    std::vector<zd> v(n), pv(n), wv(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        double nx = 0;
+        for (int i = k + 1; i < n; ++i)
+            nx += std::norm(at(i, k));
+        nx = std::sqrt(nx);
+        if (nx == 0)
+            continue;
+        const zd x0 = at(k + 1, k);
+        const double ax0 = std::abs(x0);
+        const zd ph = ax0 > 0 ? x0 / ax0 : zd(1, 0);
+        const zd alpha = -ph * nx;  // the image of x: alpha e_{k+1}
+        // v = (x - alpha e_{k+1}) / |x - alpha e_{k+1}|
+        for (int i = 0; i <= k; ++i)
+            v[i] = 0;
+        for (int i = k + 1; i < n; ++i)
+            v[i] = at(i, k);
+        v[k + 1] -= alpha;
+        double nv = 0;
+        for (int i = k + 1; i < n; ++i)
+            nv += std::norm(v[i]);
+        nv = std::sqrt(nv);
+        if (nv == 0)
+            continue;
+        for (int i = k + 1; i < n; ++i)
+            v[i] /= nv;
+        // p = 2 A v over rows and columns k .. n-1 (column k included, so that
+        // the reflected column comes out of the same update)
+        for (int i = k; i < n; ++i) {
+            zd sacc(0, 0);
+            for (int j = k + 1; j < n; ++j)
+                sacc += at(i, j) * v[j];
+            pv[i] = 2.0 * sacc;
+        }
+        zd vhp(0, 0);
+        for (int i = k + 1; i < n; ++i)
+            vhp += std::conj(v[i]) * pv[i];
+        for (int i = k; i < n; ++i)
+            wv[i] = pv[i] - vhp * v[i];
+        for (int i = k; i < n; ++i)
+            for (int j = k; j < n; ++j)
+                at(i, j) -= v[i] * std::conj(wv[j]) + wv[i] * std::conj(v[j]);
+        // exact zeros below the sub-diagonal and the reflected entry
+        for (int i = k + 2; i < n; ++i)
+            at(i, k) = at(k, i) = 0;
+        at(k + 1, k) = alpha;
+        at(k, k + 1) = std::conj(alpha);
+        // Q <- Q H_k
+        for (int i = 0; i < n; ++i) {
+            zd qv(0, 0);
+            for (int j = k + 1; j < n; ++j)
+                qv += Q[(size_t)i * n + j] * v[j];
+            qv *= 2.0;
+            for (int j = k + 1; j < n; ++j)
+                Q[(size_t)i * n + j] -= qv * std::conj(v[j]);
+        }
+    }
+    // real tridiagonal: d (diagonal), e[k] between k and k+1
+    std::vector<double> d(n), e(n, 0.0);
+    std::vector<zd> D(n);
+    D[0] = 1;
+    for (int k = 0; k < n; ++k)
+        d[k] = at(k, k).real();
+    for (int k = 0; k + 1 < n; ++k) {
+        const zd b = at(k + 1, k);
+        const double ab = std::abs(b);
+        e[k] = ab;
+        D[k + 1] = ab > 0 ? D[k] * (b / ab) : D[k];
+    }
     V.assign((size_t)n * n, zd(0, 0));
     for (int i = 0; i < n; ++i)
-        V[(size_t)i * n + i] = 1.0;
-    auto at = [&](int i, int j) -> zd & { return A[(size_t)i * n + j]; };
-    double fro = 0;
-    for (const zd &z : A)
-        fro += std::norm(z);
-    fro = std::sqrt(fro);
-    int sweep = 0;
-    for (; sweep < 60; ++sweep) {
-        double off = 0;
-        for (int i = 0; i < n; ++i)
-            for (int j = i + 1; j < n; ++j)
-                off += std::norm(at(i, j));
-        if (std::sqrt(2 * off) <= 1e-16 * fro || fro == 0)
-            break;
-        for (int p = 0; p < n - 1; ++p) {
-            for (int q = p + 1; q < n; ++q) {
-                const zd apq = at(p, q);
-                const double mag = std::abs(apq);
-                if (mag == 0 || mag < 1e-300)
-                    continue;
-                const double app = at(p, p).real(), aqq = at(q, q).real();
-                const double tau = (aqq - app) / (2 * mag);
-                const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1 + tau * tau));
-                const double c = 1 / std::sqrt(1 + t * t), s = t * c;
-                const zd e = apq / mag;              // e^{i phi}
-                const zd se = s * e, sec = s * std::conj(e);
-                // columns: A <- A J
-                for (int k = 0; k < n; ++k) {
-                    const zd akp = at(k, p), akq = at(k, q);
-                    at(k, p) = c * akp - sec * akq;
-                    at(k, q) = se * akp + c * akq;
+        for (int j = 0; j < n; ++j)
+            V[(size_t)i * n + j] = Q[(size_t)i * n + j] * D[j];
+    // implicit QL on (d, e)
+    int iters = 0;
+    for (int l = 0; l < n; ++l) {
+        for (int guard = 0; guard < 60; ++guard) {
+            int m = l;
+            for (; m + 1 < n; ++m) {
+                // e[m] is negligible when adding it to |d[m]| + |d[m+1]| changes nothing
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                volatile double sum = std::fabs(e[m]) + dd;
+                if (sum == dd)
+                    break;
+            }
+            if (m == l)
+                break;
+            ++iters;
+            // Wilkinson-type shift from the leading 2 x 2 block
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+            double s = 1, c = 1, p = 0;
+            int i = m - 1;
+            for (; i >= l; --i) {
+                const double f = s * e[i], b = c * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0) {
+                    d[i + 1] -= p;
+                    e[m] = 0;
+                    break;
                 }
-                // rows: A <- J^H A
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0 * c * b;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - b;
                 for (int k = 0; k < n; ++k) {
-                    const zd apk = at(p, k), aqk = at(q, k);
-                    at(p, k) = c * apk - se * aqk;
-                    at(q, k) = sec * apk + c * aqk;
-                }
-                at(p, q) = 0;
-                at(q, p) = 0;
-                at(p, p) = at(p, p).real();
-                at(q, q) = at(q, q).real();
-                for (int k = 0; k < n; ++k) {
-                    zd &vp = V[(size_t)k * n + p];
-                    zd &vq = V[(size_t)k * n + q];
-                    const zd a0 = vp, b0 = vq;
-                    vp = c * a0 - sec * b0;
-                    vq = se * a0 + c * b0;
+                    const zd zf = V[(size_t)k * n + i + 1], zi = V[(size_t)k * n + i];
+                    V[(size_t)k * n + i + 1] = s * zi + c * zf;
+                    V[(size_t)k * n + i] = c * zi - s * zf;
                 }
             }
+            if (r == 0 && i >= l)
+                continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0;
         }
     }
     // sort descending
     std::vector<int> idx(n);
     std::iota(idx.begin(), idx.end(), 0);
-    std::vector<double> d(n);
-    for (int i = 0; i < n; ++i)
-        d[i] = at(i, i).real();
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] > d[b]; });
     w.resize(n);
     std::vector<zd> Vs((size_t)n * n);
@@ -82,7 +158,7 @@ int eigh_jacobi(int n, std::vector<zd> &A, std::vector<double> &w, std::vector<z
             Vs[(size_t)k * n + j] = V[(size_t)k * n + idx[j]];
     }
     V.swap(Vs);
-    return sweep;
+    return iters;
 }
 
 void pinv_tall(int m, int k, const std::vector<zd> &U, std::vector<zd> &P, double rcond) {
@@ -97,7 +173,7 @@ void pinv_tall(int m, int k, const std::vector<zd> &U, std::vector<zd> &P, doubl
         }
     std::vector<double> lam;
     std::vector<zd> W;
-    eigh_jacobi(k, H, lam, W);
+    eigh(k, H, lam, W);
     const double lmax = lam.empty() ? 0 : lam[0];
     // M = W diag(1/lam) W^H
     std::vector<zd> Mi((size_t)k * k, zd(0, 0));

@@ -1,7 +1,7 @@
 // Small dense FP64 linear algebra of the plan (host side): Hermitian
-// eigen-decomposition by cyclic Jacobi rotations, and a pseudo-inverse of a
-// tall matrix through its Gram matrix.  Sizes are the separation's sample
-// counts (r <= a few hundred), so O(r^3) host work is negligible.
+// eigen-decomposition (Householder tridiagonalisation and implicit QL) and a
+// pseudo-inverse of a tall matrix through its Gram matrix.  Sizes are the
+// separation's sample counts (r <= 256).
 #pragma once
 
 #include <complex>
@@ -12,8 +12,10 @@ namespace fio {
 using zd = std::complex<double>;
 
 // A: n x n Hermitian (row-major, overwritten).  w: eigenvalues, descending.
-// V: n x n, eigenvectors as columns (row-major).  Returns sweeps used.
-int eigh_jacobi(int n, std::vector<zd> &A, std::vector<double> &w, std::vector<zd> &V);
+// V: n x n, eigenvectors as columns (row-major).
+// Householder tridiagonalisation and implicit QL, O(n^3) with a small
+// constant; returns the QL iterations.
+int eigh(int n, std::vector<zd> &A, std::vector<double> &w, std::vector<zd> &V);
 
 // P = pinv(U) for U (m x k, m >= k, row-major), singular values below
 // rcond * s_max discarded.  P is k x m (row-major).

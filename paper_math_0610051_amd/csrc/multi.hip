@@ -4,9 +4,11 @@
 // sequence is captured into a HIP graph.  The graph and the device tables are
 // cached in the first plan and replayed while the instance list (plans and
 // batch sizes) stays the same; new data pointers only refresh the argument
-// table.  Instance lists the fused path cannot take (mixed kernel widths, a
-// batch larger than a plan's workspace, or one plan listed twice, whose single
-// workspace cannot hold two instances at once) run instance after instance.
+// table.  Instances of different kernel widths share the launch of the
+// widest width.  Instance lists the fused path cannot take (mixed factor
+// modes, a batch larger than a plan's workspace, or one plan listed twice,
+// whose single workspace cannot hold two instances at once) run instance
+// after instance.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -124,7 +126,12 @@ static fio_status build_state(MultiState &st, int n, const fio_plan_t *plans, co
     FIO_HIP_TRY(hipMemcpy(st.d_cols, cols.data(), sizeof(MultiColItem) * cols.size(), hipMemcpyHostToDevice));
     FIO_HIP_TRY(hipMemcpy(st.d_tiles, tiles.data(), sizeof(MultiTile) * tiles.size(), hipMemcpyHostToDevice));
     st.ml.precision = plans[0]->precision;
-    st.ml.w = plans[0]->w;
+    // one interpolation kernel of the widest stencil serves every instance:
+    // an instance of width w < W computes its weights with its own w and
+    // beta, which vanish beyond w/2, so the extra taps add exact zeros
+    st.ml.w = 0;
+    for (int i = 0; i < n; ++i)
+        st.ml.w = std::max(st.ml.w, plans[i]->w);
     st.ml.inst = st.d_inst;
     st.ml.rows = st.d_rows;
     st.ml.cols = st.d_cols;
@@ -166,7 +173,7 @@ fio_status multi_apply(int n, const fio_plan_t *plans, const void *const *fhat, 
                        hipStream_t s) {
     bool fused = true;
     for (int i = 0; i < n; ++i)
-        if (plans[i]->w != plans[0]->w || plans[i]->regen != plans[0]->regen || B[i] > plans[i]->bchunk)
+        if (plans[i]->regen != plans[0]->regen || B[i] > plans[i]->bchunk)
             fused = false;
     // a plan listed twice would have both instances in its one workspace at once
     for (int i = 0; fused && i < n; ++i)

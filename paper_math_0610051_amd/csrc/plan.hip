@@ -6,7 +6,7 @@
 //      box (Section 3.4), and an oversampled FFT grid for the type-2 NUFFT;
 //   3. per wedge, the randomized separation of exp(2 pi i Phi_ell) (Section 3.2):
 //      r sampled columns, their FP64 Gram matrix reduced on the GPU, a host
-//      Jacobi eigen-decomposition (the SVD of A_[C] through its Gram matrix),
+//      Hermitian eigen-decomposition (the SVD of A_[C] through its Gram matrix),
 //      rank q from the singular-value threshold, r sampled rows and the
 //      pseudo-inverse U_[R]^+, the compressed form A_[C] (V S^-1) U_[R]^+ A_[R]
 //      of eq. (probnewfac), an s x s error estimate (Section 4), and adaptive
@@ -516,7 +516,7 @@ fio_status separate_wedge(fio_plan_s *P, int l, const double2 *d_xcoef, DeviceSc
             return gs;
         std::vector<double> lam;
         std::vector<zd> V;
-        eigh_jacobi(rc, G, lam, V);
+        eigh(rc, G, lam, V);
         const double s1 = std::sqrt(std::max(lam[0], 0.0));
         int q = 0;
         while (q < rc && std::sqrt(std::max(lam[q], 0.0)) > thr * s1)
@@ -699,6 +699,28 @@ static fio_status store_factors(fio_plan_s *P, const double2 *d_xcoef, bool exac
     return FIO_OK;
 }
 
+// Default number of equiangular wedges.  Section 1.3 takes L ~ sqrt(N) with
+// a free constant.  The residual phase of a wedge grows like
+// S |xi| (theta - theta_ell)^2 / 2, with S = max |grad_xi h| the phase's
+// strength, so its peak S (N / sqrt 2) (pi / L)^2 / 2 is held at 0.75 or
+// below (the c1/c2 family at scale 1 stays on 8 ceil(sqrt(N) / 8)); L is
+// never below 8 ceil(sqrt(N) / 8) and is rounded up to a multiple of 8.
+int default_wedge_count(int N, const Phase &ph) {
+    const double a0 = std::fabs(ph.p[0]);
+    double S = 0;
+    switch (ph.kind) {
+    case 1: S = a0; break;
+    case 2: S = a0 * 3.0 / 16.0; break;
+    case 3: S = a0 * (1.0 + std::fabs(ph.p[1])); break;
+    case 4:
+    case 5: S = a0; break;
+    default: S = 0; break;
+    }
+    const int base = 8 * (int)std::ceil(std::sqrt((double)N) / 8.0);
+    const double Ls = kTwoPi / 2 * std::sqrt(S * N / (std::sqrt(2.0) * 1.5));
+    return std::max(base, 8 * (int)std::ceil(Ls / 8.0));
+}
+
 // Partition, NUFFT kernel, shears, boxes, grids and FFT plans.
 static fio_status plan_geometry(fio_plan_s *P) {
     const int N = P->N;
@@ -708,8 +730,10 @@ static fio_status plan_geometry(fio_plan_s *P) {
         partition_coronae(N, P->wedge_of, thetas);
     } else {
         int L = P->opt.n_wedges;
+        // a learned network fixes the partition it was trained on
+        const LearnedModel *net = static_cast<const LearnedModel *>(P->opt.learned);
         if (L <= 0)
-            L = 8 * (int)std::ceil(std::sqrt((double)N) / 8.0);
+            L = net && net->N == N ? net->L : default_wedge_count(N, P->phase);
         partition_equiangular(N, L, P->wedge_of, thetas);
     }
     P->L = (int)thetas.size();

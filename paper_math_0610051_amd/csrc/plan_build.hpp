@@ -17,6 +17,7 @@ struct DeviceScratch {
     ~DeviceScratch();
 };
 
+int default_wedge_count(int N, const Phase &ph);
 void partition_equiangular(int N, int L, std::vector<int> &ids, std::vector<double> &thetas);
 void partition_coronae(int N, std::vector<int> &ids, std::vector<double> &thetas);
 void wedge_geometry(int N, WedgeHost &W);

@@ -2,7 +2,7 @@
 
 The library must load on a machine without a GPU, export every function the
 header declares, reject bad arguments before touching a device, and its
-host linear algebra (the plan's Jacobi eigen-solver) must be right.
+host linear algebra (the plan's Hermitian eigen-solver) must be right.
 """
 import ctypes
 import os
@@ -47,8 +47,8 @@ def test_default_options(lib):
     assert o.sigma == 2.0 and o.r0 == 32 and o.verify_samples == 200
 
 
-@pytest.mark.parametrize("n", [1, 2, 5, 16, 33])
-def test_host_jacobi_eigh_matches_lapack(n):
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 33, 128, 256])
+def test_host_eigh_matches_lapack(n):
     rng = np.random.default_rng(n)
     A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
     A = A + A.conj().T
@@ -70,7 +70,8 @@ def test_host_eigh_on_gram_of_unimodular_columns():
     w, V = fio.host_eigh(G)
     s = np.linalg.svd(A, compute_uv=False)
     big = s ** 2 > 1e-12 * s[0] ** 2
-    np.testing.assert_allclose(w[big], (s ** 2)[big], rtol=1e-6)
+    # normwise backward stable: eigenvalue errors of order eps * |G|
+    np.testing.assert_allclose(w[big], (s ** 2)[big], rtol=1e-6, atol=1e-14 * s[0] ** 2)
 
 
 def _plan_status(N=64, kind=2, tol=1e-4, amp_kind=0, **opts):
@@ -152,3 +153,20 @@ def test_plan_files_are_checked_before_device_use(lib, tmp_path):
     old.write_bytes(b"FIOPLAN1" + (1).to_bytes(4, "little") + bytes(64))
     assert lib.fio_plan_load(str(old).encode(), ctypes.byref(h)) == fio.FIO_EINVAL
     assert b"version" in lib.fio_last_error()
+
+
+def test_host_eigh_degenerate_and_structured_spectra():
+    """Repeated eigenvalues, a zero block, and a matrix already diagonal or
+    tridiagonal (reflectors of zero columns are skipped)."""
+    rng = np.random.default_rng(7)
+    n = 40
+    Qm, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    lam = np.concatenate([np.full(10, 3.0), np.zeros(10), np.linspace(-2, 1, 20)])
+    for A in (Qm @ np.diag(lam) @ Qm.conj().T, np.diag(lam).astype(complex),
+              np.diag(lam).astype(complex) + np.diag(np.full(n - 1, 0.5j), 1) + np.diag(np.full(n - 1, -0.5j), -1)):
+        A = 0.5 * (A + A.conj().T)
+        w, V = fio.host_eigh(A)
+        ref = np.linalg.eigvalsh(A)[::-1]
+        np.testing.assert_allclose(w, ref, atol=1e-12 * max(1, np.abs(ref).max()))
+        assert np.max(np.abs(A @ V - V * w)) < 1e-11 * max(1, np.abs(ref).max())
+        assert np.max(np.abs(V.conj().T @ V - np.eye(n))) < 1e-12

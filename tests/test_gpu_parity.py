@@ -544,3 +544,31 @@ def test_multi_rejects_or_serialises_a_repeated_plan():
     a1, a2 = p.apply(f1), p.apply(f2)
     torch.cuda.synchronize()
     assert torch.equal(u1, a1) and torch.equal(u2, a2)
+
+
+def test_multi_mixed_widths_in_one_launch():
+    """Instances whose tolerances need different kernel widths share one fused
+    launch (the widest stencil, each instance weighting with its own width):
+    the result equals each plan's own apply to rounding and meets its budget."""
+    from paper_math_0610051_amd import apply_multi
+    rng = np.random.default_rng(16)
+    specs = [(64, "c1c2", (1.0,), 1e-2, 2), (96, "radial", (0.05, 0.5), 1e-4, 1), (80, "c1c2", (0.8,), 2e-6, 1)]
+    plans, fh, host = [], [], []
+    for N, kind, params, tol, B in specs:
+        plans.append(_plan(N, kind, params, tol))
+        h = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=B))
+        host.append(h)
+        fh.append(_dev(h))
+    widths = sorted({p.info()["kernel_width"] for p in plans})
+    print("  kernel widths %s" % widths)
+    assert len(widths) >= 2
+    outs = apply_multi(plans, fh)
+    torch.cuda.synchronize()
+    for (N, kind, params, tol, B), p, f, h, u in zip(specs, plans, fh, host, outs):
+        single = p.apply(f)
+        torch.cuda.synchronize()
+        a = u.cpu().numpy().astype(np.complex128).reshape(B, N * N)
+        b = single.cpu().numpy().astype(np.complex128).reshape(B, N * N)
+        assert ref.rel_l2(a, b) < 1e-6
+        exact = od.direct(N, ref.KINDS[kind], params, h, np.arange(N * N)).reshape(B, N * N)
+        assert ref.rel_l2(a, exact) <= tol
