@@ -13,6 +13,7 @@ Other workloads (each prints its own JSON line):
   --workload uneven   32 instances, N in {128, ..., 1024}, one fused launch
   --workload learned  network-factor plan vs exact plan at N = 1024
   --workload paper    the paper's Table 3 / Table 4 examples, N = 64 ... 512
+  --workload adjoint  the adjoint L* on the N = 1024 plan, 8 right-hand sides
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batched]
 """
@@ -444,6 +445,68 @@ def run_learned(args):
     print(json.dumps(res), flush=True)
 
 
+def run_adjoint(args):
+    """The adjoint apply (Section 3.5) on the benchmark's plan: B = 8
+    complex-Gaussian grids g at N = 1024 -> Fourier coefficients of L*g,
+    timed like the forward, and checked per right-hand side against the FP64
+    adjoint direct sum at sampled frequencies."""
+    import numpy as np
+    import torch
+
+    import fio_inputs as fi
+    from oracle import direct as od
+
+    N, B = args.N, args.batch
+    fixed = tuple(float(v) for v in args.plan_params.split(",")) if args.plan_params else (40, 2.0, 0.4, 0.15, 5)
+    plan, plan_s, best = tuned_plan(N, args.tol, B, fixed, args.factor_mode)
+    info = plan.info()
+    rng = fi.rng_for(5, 0)
+    g = fi.complex_gaussian(N, rng, B=B)
+    gd = torch.from_numpy(g.astype(np.complex64)).cuda()
+    out = torch.empty_like(gd)
+    for _ in range(args.warmup):
+        plan.apply_adjoint(gd, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.apply_adjoint(gd, out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # forward on the same plan, for comparison
+    fwd = torch.empty_like(gd)
+    plan.apply(gd, fwd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.apply(gd, fwd)
+    torch.cuda.synchronize()
+    el_f = time.perf_counter() - t0
+    od.build(force=False)
+    ks = np.sort(np.random.default_rng(77).choice(N * N, size=args.adjoint_samples, replace=False))
+    log("adjoint oracle check on %d frequencies x %d RHS" % (ks.size, B))
+    refv = od.direct_adjoint(N, 2, (1.0,), g, ks)
+    got = out.cpu().numpy().reshape(B, N * N)[:, ks].astype(np.complex128)
+    errs = [float(np.linalg.norm(got[b] - refv[b]) / np.linalg.norm(refv[b])) for b in range(B)]
+    res = dict(metric="FIO adjoint applies/s at N=%d, rel-l2<=%g" % (N, args.tol),
+               value=B * args.steps / el, unit="applies/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=1e3 * el / args.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="c64 (fp32 data, fp64 phase and points)", data="synthetic",
+               config=dict(workload="adjoint L* of the N=%d c1/c2 plan (L=%d, sigma=%g, w=%d, ranks %d..%d), "
+                                    "B=%d complex-Gaussian grids" % (N, info["L"], info["sigma"],
+                                                                      info["kernel_width"], info["min_rank"],
+                                                                      info["max_rank"], B),
+                           plan_s=plan_s),
+               forward_applies_per_s=B * args.steps / el_f, rel_l2_vs_oracle=max(errs),
+               rel_l2_vs_oracle_per_rhs=errs, oracle_samples=int(ks.size), roofline=None, cpu_baseline=None)
+    bad = max(errs) > args.tol
+    if bad:
+        res["invalid"] = "relative l2 error %.3e above the budget %.1e" % (max(errs), args.tol)
+        res["value"] = None
+    print(json.dumps(res), flush=True)
+    if bad:
+        sys.exit(3)
+
+
 # The paper's Tables 3 and 4 (Matlab, one 2.6 GHz CPU): N -> (eps, preprocessing s, evaluation s, error, MB).
 PAPER_TABLE3 = {64: (2.44e-3, 2.06, 3.89, 2.08e-3, 0.76), 128: (6.10e-4, 10.9, 24.5, 8.02e-4, 1.26),
                 256: (1.53e-4, 81.0, 165.0, 1.00e-4, 2.01), 512: (3.81e-5, 467.0, 988.0, 4.22e-5, 3.06)}
@@ -507,7 +570,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("batched", "batch512", "uneven", "learned", "paper"), default="batched")
+    ap.add_argument("--workload", choices=("batched", "batch512", "uneven", "learned", "paper", "adjoint"),
+                    default="batched")
+    ap.add_argument("--adjoint-samples", type=int, default=2048)
     ap.add_argument("--N", type=int, default=1024)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--tol", type=float, default=1e-4)
@@ -531,7 +596,7 @@ def main():
               "with one sum of the partial outputs); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     {"batched": run_batched, "batch512": run_batch512, "uneven": run_uneven,
-     "learned": run_learned, "paper": run_paper}[args.workload](args)
+     "learned": run_learned, "paper": run_paper, "adjoint": run_adjoint}[args.workload](args)
 
 
 if __name__ == "__main__":
