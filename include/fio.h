@@ -192,7 +192,12 @@ fio_status fio_apply_batch(fio_plan_t plan, int B, const void *fhat, void *u, vo
  * exact adjoint of the computed forward map up to rounding.  An inverse 2-D
  * DFT of hhat gives (L*g)(x).  It uses the plan's workspace, so a plan runs
  * one forward or adjoint apply at a time.  B right-hand sides are back to
- * back, as in fio_apply_batch. */
+ * back, as in fio_apply_batch.  The first adjoint call on a plan also lists,
+ * for every block of each wedge's grid, the grid points whose stencils touch
+ * it (about 8.4 bytes per grid point and wedge of device memory, owned by the
+ * plan); that call synchronises the device.  The sums of the spreading are
+ * formed with floating-point atomics, so the last bits can differ between
+ * runs. */
 fio_status fio_apply_adjoint(fio_plan_t plan, const void *g, void *hhat, void *stream);
 fio_status fio_apply_adjoint_batch(fio_plan_t plan, int B, const void *g, void *hhat, void *stream);
 
@@ -277,10 +282,11 @@ fio_status fio_probe_error(fio_plan_t plan, const void *fhat, const void *u, int
 fio_status fio_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Autotuner.  Builds candidate plans over the wedge count (L0 - 8 .. L0 + 16),
- * the oversampling factor (2, 2.5) and the split of tol between separation and
- * NUFFT, times an apply of B right-hand sides with HIP events and probes its
- * error with fio_probe_error; *best is the fastest candidate whose error is at
- * most 0.8 tol.  If the environment variable FIO_TUNE_CACHE names a file, a
+ * the oversampling factor (1.5, 1.75, 2, 2.5), the split of tol between
+ * separation and NUFFT and the kernel width (the bound's and one below),
+ * times an apply of B right-hand sides with HIP events and probes its error
+ * at 256 points with fio_probe_error; *best is the fastest candidate whose
+ * error is at most 0.8 tol.  If the environment variable FIO_TUNE_CACHE names a file, a
  * cached choice for the same problem is returned without tuning and new
  * choices are appended.  Copy best's fields into fio_options to use them. */
 typedef struct {

@@ -287,8 +287,11 @@ fio_status fio_apply_adjoint_batch(fio_plan_t P, int B, const void *g, void *hha
     DeviceScope ds(P->device);
     if (ds.err != hipSuccess)
         return hip_fail(ds.err, "hipSetDevice");
-    FIO_HIP_TRY(adjoint_launch(P, B, g, hhat, static_cast<hipStream_t>(stream)));
-    return FIO_OK;
+    try {
+        return adjoint_launch(P, B, g, hhat, static_cast<hipStream_t>(stream));
+    } catch (const std::bad_alloc &) {
+        return (set_error("host allocation failed"), FIO_ENOMEM);
+    }
 }
 
 fio_status fio_apply_adjoint(fio_plan_t plan, const void *g, void *hhat, void *stream) {

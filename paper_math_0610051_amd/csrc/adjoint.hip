@@ -11,8 +11,9 @@
 // rounding:
 //   k_spread    conj(gamma^x) conj(modulation) g spread onto each wedge's
 //               oversampled grid with the ES weights (the transpose of the
-//               interpolation), accumulated per tile in an LDS window and
-//               added to the grid with global atomics;
+//               interpolation), gathered per block of grid cells from the
+//               grid points whose stencils touch the block (lists built once
+//               per plan) and accumulated in LDS;
 //   k_cols_adj  FFT with the - sign along axis 1, keeping the box rows;
 //   k_rows_adj  FFT with the - sign along axis 2, keeping the box columns,
 //               then the sum over ranks with conj(gamma^xi) (1/N and the
@@ -26,11 +27,11 @@
 
 #include "adjoint.hpp"
 #include "apply.hpp"
+#include "errors.hpp"
 #include "interp_util.hpp"
 
 namespace fio {
 
-constexpr int kSpreadLdsBytes = 65536;  // LDS window of the spreading (planes of several ranks and RHS)
 
 template <typename T>
 __device__ __forceinline__ cplx<T> cconj(cplx<T> a) {
@@ -48,196 +49,267 @@ __device__ __forceinline__ void global_add(T *p, T v) {
 }
 
 // ---------------------------------------------------------------------------
-// Stage A1: spreading.  A workgroup owns a kTileX x kTileX tile of input
-// points (one per thread) and loops over the wedges.  Per wedge the stencils
-// of the tile cover a window of the oversampled grid (found as in the
-// interpolation); rounds of planes (right-hand side b, rank t) of that window
-// are accumulated in LDS and then added to G.  Windows too large for one
-// plane of LDS or wider than the grid (strongly folded warps) are added to G
-// directly.
+// Stage A1: spreading, gathered per block of the oversampled grid.  Each
+// wedge's grid is cut into kBin1 x kBin2 cell blocks; at the first adjoint
+// apply every grid point x is listed in the blocks its w x w stencil touches
+// (a point's warp and stencil do not depend on the input).  A workgroup owns
+// one block: it accumulates conj(gamma^x_t(x)) conj(exp(2 pi i psi(x))) g_b(x)
+// times the ES weights of the taps that fall in the block, for every listed
+// point and every plane (b, t), in LDS (float atomics: several points hit a
+// cell), and writes the block once with plain stores.  Every grid cell
+// belongs to exactly one block, so the grids need no clearing and no global
+// atomics are involved.
 // ---------------------------------------------------------------------------
-template <typename T, int W, bool REGEN>
-__global__ __launch_bounds__(kThreads) void k_spread(PlanArgs<T> a, const cplx<T> *__restrict__ g, long long gstride,
-                                                     int B, int bofs, int l0, int l1) {
-    extern __shared__ unsigned char smem_raw[];
-    cplx<T> *win = reinterpret_cast<cplx<T> *>(smem_raw);
-    constexpr int kCells = kSpreadLdsBytes / (int)sizeof(cplx<T>);
-    __shared__ double red[kThreads / 64][4];
-    const int N = a.N;
+constexpr int kBin1 = 16, kBin2 = 8;  // block of cells along the long (1) and short (2) grid axes
+constexpr int kBinCells = kBin1 * kBin2;
+template <typename T>
+constexpr int kSpreadPlanes = sizeof(T) == 4 ? 32 : 16;  // (RHS, rank) planes per round
+template <typename T>
+constexpr int kSpreadLds = kBinCells * (2 * kSpreadPlanes<T> + 1) * (int)sizeof(T);
+
+// Warped point of x in wedge W, its stencil's first cell on each axis
+// wrapped into [0, m), and the fractions f = u - j of the unwrapped grid
+// coordinate u = m (y' - k).  The integer reference k is the one the
+// interpolation uses for x's output tile (the floor of the tile's smallest
+// coordinate, tabulated per tile and wedge), and u, j and f are formed with
+// the interpolation's own arithmetic, so that every point spreads with
+// exactly the stencil cells and weights it is interpolated with.
+struct SpreadPoint {
+    int j1, j2;
+    double f1, f2;
+    double y1, y2;
+};
+__device__ inline double warp_coord(const WedgeDev &wd, int axis, double y1, double y2) {
+    return axis == 0 ? wd.mt[0] * y1 + wd.mt[1] * y2 : wd.mt[2] * y1 + wd.mt[3] * y2;
+}
+__device__ inline int origin_rt(double m, double y, double k, int W, double &u) {
+#pragma clang fp contract(off)
+    u = m * (y - k);
+    return (int)floor(u - 0.5 * W) + 1;
+}
+__device__ inline SpreadPoint spread_point(const Phase &ph, const WedgeDev &wd, double x1, double x2, const XCoef &c,
+                                           int W, int2 ref, double &g1, double &g2) {
+    phase_grad(ph, c, wd.e1, wd.e2, g1, g2);
+    SpreadPoint s;
+    s.y1 = x1 + g1;
+    s.y2 = x2 + g2;
+    const double yp1 = warp_coord(wd, 0, s.y1, s.y2), yp2 = warp_coord(wd, 1, s.y1, s.y2);
+    double u1, u2;
+    const int j1 = origin_rt(wd.n1, yp1, (double)ref.x, W, u1), j2 = origin_rt(wd.n2, yp2, (double)ref.y, W, u2);
+    s.f1 = u1 - j1;
+    s.f2 = u2 - j2;
+    int a = j1 % wd.n1, b = j2 % wd.n2;
+    s.j1 = a < 0 ? a + wd.n1 : a;
+    s.j2 = b < 0 ? b + wd.n2 : b;
+    return s;
+}
+
+// Integer reference of every output tile and wedge: the floor of the
+// smallest warped coordinate over the tile's points on each axis, as the
+// interpolation forms its window (block-wide minimum).
+__global__ __launch_bounds__(kThreads) void k_adj_tileref(Phase ph, int N, const WedgeDev *__restrict__ wedges,
+                                                          int2 *__restrict__ ref) {
+    __shared__ double red[kThreads / 64][2];
     const int tiles = (N + kTileX - 1) / kTileX;
-    const int tile = chunked_tile(xcd_slot(blockIdx.x, gridDim.x), tiles);
-    const int T1 = (tile / tiles) * kTileX, T2 = (tile % tiles) * kTileX;
+    const int tile = blockIdx.x, l = blockIdx.y;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int n1 = T1 + tid / kTileX, n2 = T2 + tid % kTileX;
+    const int n1 = (tile / tiles) * kTileX + tid / kTileX, n2 = (tile % tiles) * kTileX + tid % kTileX;
     const bool active = n1 < N && n2 < N;
-    const long long p = active ? (long long)n1 * N + n2 : 0;
+    const WedgeDev &wd = wedges[l];
     const double x1 = (double)n1 / N, x2 = (double)n2 / N;
-    const XCoef c = phase_xcoef(a.phase, x1, x2);
-    // this point's inputs, one per right-hand side
-    cplx<T> gv[kInterpBatch];
-#pragma unroll
-    for (int b = 0; b < kInterpBatch; ++b)
-        gv[b] = (active && b < B) ? g[b * gstride + p] : cmake<T>(0, 0);
-    // regenerated gamma^x of the tile's points follows the window in LDS
-    cplx<T> *gxl = reinterpret_cast<cplx<T> *>(smem_raw + kSpreadLdsBytes);
-    for (int l = l0; l < l1; ++l) {
-        const WedgeDev &wd = a.wedges[l];
-        if (wd.q == 0)
-            continue;
-        const int m1 = wd.n1, m2 = wd.n2, q = wd.q;
-        double g1, g2;
-        phase_grad(a.phase, c, wd.e1, wd.e2, g1, g2);
-        if constexpr (REGEN) {
-            const double2 *zc = a.zcol + wd.zc_off;
-            const double2 *zm = a.zmat + wd.zm_off;
-            for (int t = 0; t < q; ++t)
-                gxl[t * kThreads + tid] = cmake<T>(0, 0);
-            for (int cc = 0; cc < wd.zrc; ++cc) {
-                const double2 k = zc[cc];
-                double cs2, sn2;
-                residual_entry(a.phase, c, g1, g2, k.x, k.y, cs2, sn2);
-                const double2 *zr = zm + (long long)cc * q;
-                for (int t = 0; t < q; ++t) {
-                    const double2 z = zr[t];
-                    cplx<T> &o = gxl[t * kThreads + tid];
-                    o.re += (T)(cs2 * z.x - sn2 * z.y);
-                    o.im += (T)(cs2 * z.y + sn2 * z.x);
-                }
-            }
+    const XCoef c = phase_xcoef(ph, x1, x2);
+    double g1, g2;
+    phase_grad(ph, c, wd.e1, wd.e2, g1, g2);
+    const double y1 = x1 + g1, y2 = x2 + g2;
+    const double yp1 = warp_coord(wd, 0, y1, y2), yp2 = warp_coord(wd, 1, y1, y2);
+    const double mn1 = wave_min(active ? yp1 : DBL_MAX), mn2 = wave_min(active ? yp2 : DBL_MAX);
+    if (lane == 0) {
+        red[wave][0] = mn1;
+        red[wave][1] = mn2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double lo1 = red[0][0], lo2 = red[0][1];
+        for (int k = 1; k < kThreads / 64; ++k) {
+            lo1 = fmin(lo1, red[k][0]);
+            lo2 = fmin(lo2, red[k][1]);
         }
-        const double y1 = x1 + g1, y2 = x2 + g2;
-        const double yp1 = wd.mt[0] * y1 + wd.mt[1] * y2;
-        const double yp2 = wd.mt[2] * y1 + wd.mt[3] * y2;
-        double psi = wd.cvec[0] * y1 + wd.cvec[1] * y2;
-        psi -= rint(psi);
-        T cs, sn;
-        expi_t<T>(psi, cs, sn);
-        const cplx<T> cmod = cmake<T>(cs, -sn);  // conj(exp(2 pi i psi))
-        {
-            const double mn1 = wave_min(active ? yp1 : DBL_MAX), mx1 = wave_max(active ? yp1 : -DBL_MAX);
-            const double mn2 = wave_min(active ? yp2 : DBL_MAX), mx2 = wave_max(active ? yp2 : -DBL_MAX);
-            if (lane == 0) {
-                red[wave][0] = mn1;
-                red[wave][1] = mx1;
-                red[wave][2] = mn2;
-                red[wave][3] = mx2;
+        ref[(long long)l * tiles * tiles + tile] = make_int2((int)floor(lo1), (int)floor(lo2));
+    }
+}
+
+__device__ inline int2 tile_ref(const int2 *ref, int N, int l, int n1, int n2) {
+    const int tiles = (N + kTileX - 1) / kTileX;
+    return ref[(long long)l * tiles * tiles + (n1 / kTileX) * tiles + n2 / kTileX];
+}
+
+// Distinct blocks (at most 4 per axis) that the W cells j, j+1, ... (mod m) touch.
+__device__ inline int stencil_bins(int j, int W, int m, int bb, int *bins) {
+    int n = 0, last = -1;
+    for (int i = 0; i < W; ++i) {
+        int c = j + i;
+        if (c >= m)
+            c -= m;
+        const int b = c / bb;
+        if (b != last) {
+            bins[n++] = b;
+            last = b;
+        }
+    }
+    return n;
+}
+
+// Bin builder, pass 0 counts and pass 1 fills: thread = (grid point, wedge).
+__global__ void k_adj_bins(Phase ph, int N, const WedgeDev *__restrict__ wedges, int W, const int2 *__restrict__ ref,
+                           const long long *__restrict__ wbase, const int *__restrict__ nb2, int pass,
+                           unsigned *__restrict__ counter, const long long *__restrict__ off, int *__restrict__ pts) {
+    const long long NN = (long long)N * N;
+    const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int l = blockIdx.y;
+    if (p >= NN)
+        return;
+    const WedgeDev &wd = wedges[l];
+    if (wd.q == 0)
+        return;
+    const int n1 = (int)(p / N), n2 = (int)(p % N);
+    const double x1 = (double)n1 / N, x2 = (double)n2 / N;
+    const XCoef c = phase_xcoef(ph, x1, x2);
+    double g1, g2;
+    const SpreadPoint sp = spread_point(ph, wd, x1, x2, c, W, tile_ref(ref, N, l, n1, n2), g1, g2);
+    int b1[4], b2[4];
+    const int k1 = stencil_bins(sp.j1, W, wd.n1, kBin1, b1), k2 = stencil_bins(sp.j2, W, wd.n2, kBin2, b2);
+    for (int a = 0; a < k1; ++a)
+        for (int b = 0; b < k2; ++b) {
+            const long long bin = wbase[l] + (long long)b1[a] * nb2[l] + b2[b];
+            const unsigned slot = atomicAdd(&counter[bin], 1u);
+            if (pass == 1)
+                pts[off[bin] + slot] = (int)p;
+        }
+}
+
+template <typename T, int W, bool REGEN>
+__global__ __launch_bounds__(kThreads) void k_spread(PlanArgs<T> a, const AdjBin *__restrict__ bins,
+                                                     const int *__restrict__ pts, const int2 *__restrict__ ref,
+                                                     const cplx<T> *__restrict__ g, long long gstride, int B,
+                                                     int bofs) {
+    extern __shared__ unsigned char smem_raw[];
+    // [cell][plane of the round][re, im] with an odd cell stride of 2 kPlanes + 1
+    // words, so that the cells of one plane fall in different LDS banks
+    T *win = reinterpret_cast<T *>(smem_raw);
+    constexpr int kPlanes = kSpreadPlanes<T>;
+    constexpr int kCellStride = 2 * kPlanes + 1;
+    const AdjBin bin = bins[blockIdx.x];
+    const WedgeDev &wd = a.wedges[bin.l];
+    const int N = a.N, m1 = wd.n1, m2 = wd.n2, q = wd.q, tid = threadIdx.x;
+    const int nplanes = B * q;
+    cplx<T> *G0 = a.G + (long long)bofs * a.G_stride + wd.G_off;
+    const cplx<T> *gx0 = a.gx + wd.gx_off;
+    // a stride prime to the list length visits every entry once
+    const int stride = bin.n % 7919 ? 7919 : (bin.n % 7927 ? 7927 : 1);
+    for (int p0 = 0; p0 < nplanes; p0 += kPlanes) {
+        const int np = min(kPlanes, nplanes - p0);
+        for (int e = tid; e < kBinCells * kCellStride; e += kThreads)
+            win[e] = T(0);
+        __syncthreads();
+        for (int k = tid; k < bin.n; k += kThreads) {
+            // The list runs in point order, and neighbouring points share
+            // stencil cells: lanes take entries a prime stride apart, so that
+            // the lanes of one LDS atomic hit different cells.
+            const int p = pts[bin.off + (int)(((long long)k * stride) % bin.n)];
+            const int n1 = p / N, n2 = p - n1 * N;
+            const double x1 = (double)n1 / N, x2 = (double)n2 / N;
+            const XCoef c = phase_xcoef(a.phase, x1, x2);
+            double g1, g2;
+            const SpreadPoint sp = spread_point(a.phase, wd, x1, x2, c, W, tile_ref(ref, N, bin.l, n1, n2), g1, g2);
+            double psi = wd.cvec[0] * sp.y1 + wd.cvec[1] * sp.y2;
+            psi -= rint(psi);
+            T cs, sn;
+            expi_t<T>(psi, cs, sn);
+            const cplx<T> cmod = cmake<T>(cs, -sn);  // conj(exp(2 pi i psi))
+            const T f1 = (T)sp.f1, f2 = (T)sp.f2;
+            // taps inside this block: rows r0 + i1 in [0, kBin1), columns c0 + i2 in [0, kBin2)
+            int r0 = sp.j1 - bin.o1, c0 = sp.j2 - bin.o2;
+            if (r0 < -W)
+                r0 += m1;
+            else if (r0 >= kBin1)
+                r0 -= m1;
+            if (c0 < -W)
+                c0 += m2;
+            else if (c0 >= kBin2)
+                c0 -= m2;
+            T w1[W], w2[W];
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                w1[i] = (r0 + i >= 0 && r0 + i < kBin1) ? es_weight<T>(f1 - T(i), a.two_over_w, a.beta) : T(0);
+                w2[i] = (c0 + i >= 0 && c0 + i < kBin2) ? es_weight<T>(f2 - T(i), a.two_over_w, a.beta) : T(0);
+            }
+            cplx<T> gxr[REGEN ? kRegenMaxRank : 1];
+            if constexpr (REGEN) {
+                const double2 *zc = a.zcol + wd.zc_off;
+                const double2 *zm = a.zmat + wd.zm_off;
+                double ar[kRegenMaxRank], ai[kRegenMaxRank];
+#pragma unroll
+                for (int t = 0; t < kRegenMaxRank; ++t)
+                    ar[t] = ai[t] = 0;
+                for (int cc = 0; cc < wd.zrc; ++cc) {
+                    const double2 kk = zc[cc];
+                    double cs2, sn2;
+                    residual_entry(a.phase, c, g1, g2, kk.x, kk.y, cs2, sn2);
+                    const double2 *zr = zm + (long long)cc * q;
+#pragma unroll
+                    for (int t = 0; t < kRegenMaxRank; ++t)
+                        if (t < q) {
+                            const double2 z = zr[t];
+                            ar[t] += cs2 * z.x - sn2 * z.y;
+                            ai[t] += cs2 * z.y + sn2 * z.x;
+                        }
+                }
+#pragma unroll
+                for (int t = 0; t < kRegenMaxRank; ++t)
+                    gxr[t] = cmake<T>((T)ar[t], (T)ai[t]);
+            }
+            for (int kp = 0; kp < np; ++kp) {
+                const int pl = p0 + kp, b = pl / q, t = pl - b * q;
+                cplx<T> gx;
+                if constexpr (REGEN) {
+                    gx = gxr[0];
+#pragma unroll
+                    for (int tt = 1; tt < kRegenMaxRank; ++tt)
+                        if (tt == t)
+                            gx = gxr[tt];
+                } else {
+                    gx = gx0[(long long)p * q + t];
+                }
+                const cplx<T> v = cmul(cconj(gx), cmul(cmod, g[b * gstride + p]));
+#pragma unroll
+                for (int i1 = 0; i1 < W; ++i1) {
+                    if (w1[i1] == T(0))
+                        continue;
+                    const T ar = w1[i1] * v.re, ai = w1[i1] * v.im;
+                    const int rowc = (r0 + i1) * kBin2;
+#pragma unroll
+                    for (int i2 = 0; i2 < W; ++i2)
+                        if (w2[i2] != T(0)) {
+                            T *cellp = win + (rowc + c0 + i2) * kCellStride + 2 * kp;
+                            lds_add(cellp, w2[i2] * ar);
+                            lds_add(cellp + 1, w2[i2] * ai);
+                        }
+                }
             }
         }
         __syncthreads();
-        double lo1 = red[0][0], hi1 = red[0][1], lo2 = red[0][2], hi2 = red[0][3];
-#pragma unroll
-        for (int k = 1; k < kThreads / 64; ++k) {
-            lo1 = fmin(lo1, red[k][0]);
-            hi1 = fmax(hi1, red[k][1]);
-            lo2 = fmin(lo2, red[k][2]);
-            hi2 = fmax(hi2, red[k][3]);
+        // the block's cells, all ranks of a cell together (G is [j2][j1][rank])
+        for (int e = tid; e < kBinCells * np; e += kThreads) {
+            const int cell = e / np, kp = e - cell * np;
+            const int rr = cell / kBin2, cc = cell - rr * kBin2;
+            const int gr = bin.o1 + rr, gc = bin.o2 + cc;
+            if (gr >= m1 || gc >= m2)
+                continue;
+            const int pl = p0 + kp, b = pl / q, t = pl - b * q;
+            const T *src = win + cell * kCellStride + 2 * kp;
+            G0[(long long)b * a.G_stride + ((long long)gc * m1 + gr) * q + t] = cmake<T>(src[0], src[1]);
         }
-        __syncthreads();  // red is rewritten by the next wedge
-        const double k1 = floor(lo1), k2 = floor(lo2);
-        double u1, u2, ue;
-        const int j1 = stencil_origin<W>(m1, yp1, k1, u1), j2 = stencil_origin<W>(m2, yp2, k2, u2);
-        const int J1 = stencil_origin<W>(m1, lo1, k1, ue), X1 = stencil_origin<W>(m1, hi1, k1, ue);
-        const int J2 = stencil_origin<W>(m2, lo2, k2, ue), X2 = stencil_origin<W>(m2, hi2, k2, ue);
-        const T f1 = (T)(u1 - j1), f2 = (T)(u2 - j2);
-        T w1[W], w2[W];
-#pragma unroll
-        for (int i = 0; i < W; ++i) {
-            w1[i] = es_weight<T>(f1 - T(i), a.two_over_w, a.beta);
-            w2[i] = es_weight<T>(f2 - T(i), a.two_over_w, a.beta);
-        }
-        const int F1 = X1 - J1 + W, F2 = X2 - J2 + W;
-        const int cells = F1 * F2;
-        const cplx<T> *gxp = a.gx + wd.gx_off + p * q;
-        cplx<T> *G0 = a.G + (long long)bofs * a.G_stride + wd.G_off;
-        // grid cell of window row rr / column cc: 0 <= r0 < m1 and rr < F1 <= m1,
-        // so one wrap brings r0 + rr onto the grid (likewise for axis 2)
-        const int r0 = J1 < 0 ? J1 + m1 : (J1 >= m1 ? J1 - m1 : J1);
-        const int c0 = J2 < 0 ? J2 + m2 : (J2 >= m2 ? J2 - m2 : J2);
-        const int nplanes = B * q;
-        if (cells <= kCells && F1 <= m1 && F2 <= m2) {
-            const int ppr = kCells / cells;  // planes per round
-            const int base = (j1 - J1) * F2 + (j2 - J2);
-            for (int p0 = 0; p0 < nplanes; p0 += ppr) {
-                const int np = min(ppr, nplanes - p0);
-                for (int e = tid; e < np * cells; e += kThreads)
-                    win[e] = cmake<T>(0, 0);
-                __syncthreads();
-                if (active) {
-                    for (int k = 0; k < np; ++k) {
-                        const int pl = p0 + k, b = pl / q, t = pl - b * q;
-                        const cplx<T> gx = REGEN ? gxl[t * kThreads + tid] : gxp[t];
-                        cplx<T> bv = cmake<T>(0, 0);
-#pragma unroll
-                        for (int bb = 0; bb < kInterpBatch; ++bb)
-                            if (bb == b)
-                                bv = gv[bb];
-                        const cplx<T> v = cmul(cconj(gx), cmul(cmod, bv));
-                        cplx<T> *pw = win + k * cells + base;
-#pragma unroll
-                        for (int i1 = 0; i1 < W; ++i1) {
-                            const T ar = w1[i1] * v.re, ai = w1[i1] * v.im;
-#pragma unroll
-                            for (int i2 = 0; i2 < W; ++i2) {
-                                lds_add(&pw[i1 * F2 + i2].re, w2[i2] * ar);
-                                lds_add(&pw[i1 * F2 + i2].im, w2[i2] * ai);
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
-                for (int e = tid; e < np * cells; e += kThreads) {
-                    const cplx<T> v = win[e];
-                    if (v.re == T(0) && v.im == T(0))
-                        continue;
-                    const int k = e / cells, cell = e - k * cells;
-                    const int pl = p0 + k, b = pl / q, t = pl - b * q;
-                    const int rr = cell / F2, cc = cell - rr * F2;
-                    int gr = r0 + rr, gc = c0 + cc;
-                    if (gr >= m1)
-                        gr -= m1;
-                    if (gc >= m2)
-                        gc -= m2;
-                    cplx<T> *dst = G0 + (long long)b * a.G_stride + ((long long)gc * m1 + gr) * q + t;
-                    global_add(&dst->re, v.re);
-                    global_add(&dst->im, v.im);
-                }
-                __syncthreads();  // the window is cleared for the next round
-            }
-        } else if (active) {
-            // window beyond LDS: add each stencil value to the grid directly
-            int g1i = j1 % m1, g2i = j2 % m2;
-            if (g1i < 0)
-                g1i += m1;
-            if (g2i < 0)
-                g2i += m2;
-            for (int pl = 0; pl < nplanes; ++pl) {
-                const int b = pl / q, t = pl - b * q;
-                const cplx<T> gx = REGEN ? gxl[t * kThreads + tid] : gxp[t];
-                cplx<T> bv = cmake<T>(0, 0);
-#pragma unroll
-                for (int bb = 0; bb < kInterpBatch; ++bb)
-                    if (bb == b)
-                        bv = gv[bb];
-                const cplx<T> v = cmul(cconj(gx), cmul(cmod, bv));
-                cplx<T> *G = G0 + (long long)b * a.G_stride + t;
-                for (int i1 = 0; i1 < W; ++i1) {
-                    int rr = g1i + i1;
-                    if (rr >= m1)
-                        rr -= m1;
-                    for (int i2 = 0; i2 < W; ++i2) {
-                        int cc = g2i + i2;
-                        if (cc >= m2)
-                            cc -= m2;
-                        const T wk = w1[i1] * w2[i2];
-                        cplx<T> *dst = G + ((long long)cc * m1 + rr) * q;
-                        global_add(&dst->re, wk * v.re);
-                        global_add(&dst->im, wk * v.im);
-                    }
-                }
-            }
-        }
-        if constexpr (REGEN)
-            __syncthreads();  // gxl is rewritten by the next wedge
+        __syncthreads();  // the window is cleared for the next round
     }
 }
 
@@ -348,31 +420,107 @@ __global__ __launch_bounds__(kFftThreads) void k_rows_adj(PlanArgs<T> a, const R
 // ---------------------------------------------------------------------------
 template <typename T, int W>
 static hipError_t launch_spread_w(const fio_plan_s *P, const PlanArgs<T> &a, const cplx<T> *g, long long gstride,
-                                  int B, int bofs, hipStream_t s) {
-    const int tiles = (P->N + kTileX - 1) / kTileX;
-    const size_t lds = kSpreadLdsBytes + (P->regen ? (size_t)kThreads * P->qmax * sizeof(cplx<T>) : 0);
+                                  int B, hipStream_t s) {
     if (P->regen)
-        k_spread<T, W, true><<<(unsigned)(tiles * tiles), kThreads, lds, s>>>(a, g, gstride, B, bofs, 0, P->L);
+        k_spread<T, W, true><<<(unsigned)P->n_adj_bins, kThreads, kSpreadLds<T>, s>>>(
+            a, P->d_adj_bins, P->d_adj_pts, P->d_adj_ref, g, gstride, B, 0);
     else
-        k_spread<T, W, false><<<(unsigned)(tiles * tiles), kThreads, lds, s>>>(a, g, gstride, B, bofs, 0, P->L);
+        k_spread<T, W, false><<<(unsigned)P->n_adj_bins, kThreads, kSpreadLds<T>, s>>>(
+            a, P->d_adj_bins, P->d_adj_pts, P->d_adj_ref, g, gstride, B, 0);
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_spread(const fio_plan_s *P, const PlanArgs<T> &a, const cplx<T> *g, long long gstride,
-                                int B, int bofs, hipStream_t s) {
+                                int B, hipStream_t s) {
     switch (P->w) {
-    case 4: return launch_spread_w<T, 4>(P, a, g, gstride, B, bofs, s);
-    case 5: return launch_spread_w<T, 5>(P, a, g, gstride, B, bofs, s);
-    case 6: return launch_spread_w<T, 6>(P, a, g, gstride, B, bofs, s);
-    case 7: return launch_spread_w<T, 7>(P, a, g, gstride, B, bofs, s);
-    case 8: return launch_spread_w<T, 8>(P, a, g, gstride, B, bofs, s);
-    case 10: return launch_spread_w<T, 10>(P, a, g, gstride, B, bofs, s);
-    case 12: return launch_spread_w<T, 12>(P, a, g, gstride, B, bofs, s);
-    case 14: return launch_spread_w<T, 14>(P, a, g, gstride, B, bofs, s);
-    case 16: return launch_spread_w<T, 16>(P, a, g, gstride, B, bofs, s);
+    case 4: return launch_spread_w<T, 4>(P, a, g, gstride, B, s);
+    case 5: return launch_spread_w<T, 5>(P, a, g, gstride, B, s);
+    case 6: return launch_spread_w<T, 6>(P, a, g, gstride, B, s);
+    case 7: return launch_spread_w<T, 7>(P, a, g, gstride, B, s);
+    case 8: return launch_spread_w<T, 8>(P, a, g, gstride, B, s);
+    case 10: return launch_spread_w<T, 10>(P, a, g, gstride, B, s);
+    case 12: return launch_spread_w<T, 12>(P, a, g, gstride, B, s);
+    case 14: return launch_spread_w<T, 14>(P, a, g, gstride, B, s);
+    case 16: return launch_spread_w<T, 16>(P, a, g, gstride, B, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+// The spreading blocks of every wedge and their point lists (two passes of
+// k_adj_bins: counts, then the lists at their exclusive prefix offsets).
+static fio_status build_adj_bins(fio_plan_s *P) {
+    const int L = P->L, N = P->N;
+    const long long NN = (long long)N * N;
+    std::vector<long long> wbase(L + 1, 0);
+    std::vector<int> nb1(L, 0), nb2(L, 0);
+    for (int l = 0; l < L; ++l) {
+        const WedgeDev &wd = P->wdev[l];
+        if (wd.q > 0) {
+            nb1[l] = (wd.n1 + kBin1 - 1) / kBin1;
+            nb2[l] = (wd.n2 + kBin2 - 1) / kBin2;
+        }
+        wbase[l + 1] = wbase[l] + (long long)nb1[l] * nb2[l];
+    }
+    const long long nbins = wbase[L];
+    struct Tmp {
+        std::vector<void *> p;
+        ~Tmp() {
+            for (void *v : p)
+                if (v)
+                    (void)hipFree(v);
+        }
+    } tmp;
+    long long *d_wbase = nullptr, *d_off = nullptr;
+    int *d_nb2 = nullptr;
+    unsigned *d_cnt = nullptr;
+    FIO_HIP_TRY(hipMalloc(&d_wbase, sizeof(long long) * (L + 1)));
+    tmp.p.push_back(d_wbase);
+    FIO_HIP_TRY(hipMalloc(&d_nb2, sizeof(int) * L));
+    tmp.p.push_back(d_nb2);
+    FIO_HIP_TRY(hipMalloc(&d_cnt, sizeof(unsigned) * std::max<long long>(1, nbins)));
+    tmp.p.push_back(d_cnt);
+    FIO_HIP_TRY(hipMalloc(&d_off, sizeof(long long) * std::max<long long>(1, nbins)));
+    tmp.p.push_back(d_off);
+    FIO_HIP_TRY(hipMemcpy(d_wbase, wbase.data(), sizeof(long long) * (L + 1), hipMemcpyHostToDevice));
+    FIO_HIP_TRY(hipMemcpy(d_nb2, nb2.data(), sizeof(int) * L, hipMemcpyHostToDevice));
+    const int tiles = (N + kTileX - 1) / kTileX;
+    FIO_HIP_TRY(hipMalloc(&P->d_adj_ref, sizeof(int2) * (size_t)L * tiles * tiles));
+    k_adj_tileref<<<dim3((unsigned)(tiles * tiles), (unsigned)L), kThreads>>>(P->phase, N, P->d_wedges,
+                                                                               P->d_adj_ref);
+    FIO_HIP_TRY(hipGetLastError());
+    const dim3 grid((unsigned)((NN + 255) / 256), (unsigned)L);
+    FIO_HIP_TRY(hipMemset(d_cnt, 0, sizeof(unsigned) * std::max<long long>(1, nbins)));
+    k_adj_bins<<<grid, 256>>>(P->phase, N, P->d_wedges, P->w, P->d_adj_ref, d_wbase, d_nb2, 0, d_cnt, nullptr,
+                              nullptr);
+    FIO_HIP_TRY(hipGetLastError());
+    std::vector<unsigned> cnt(nbins);
+    FIO_HIP_TRY(hipMemcpy(cnt.data(), d_cnt, sizeof(unsigned) * nbins, hipMemcpyDeviceToHost));
+    std::vector<long long> off(nbins);
+    long long total = 0;
+    for (long long i = 0; i < nbins; ++i) {
+        off[i] = total;
+        total += cnt[i];
+    }
+    std::vector<AdjBin> bins(nbins);
+    for (int l = 0; l < L; ++l)
+        for (int b1 = 0; b1 < nb1[l]; ++b1)
+            for (int b2 = 0; b2 < nb2[l]; ++b2) {
+                const long long i = wbase[l] + (long long)b1 * nb2[l] + b2;
+                bins[i] = AdjBin{l, b1 * kBin1, b2 * kBin2, (int)cnt[i], off[i]};
+            }
+    FIO_HIP_TRY(hipMalloc(&P->d_adj_pts, sizeof(int) * std::max<long long>(1, total)));
+    FIO_HIP_TRY(hipMalloc(&P->d_adj_bins, sizeof(AdjBin) * std::max<long long>(1, nbins)));
+    FIO_HIP_TRY(hipMemcpy(P->d_adj_bins, bins.data(), sizeof(AdjBin) * nbins, hipMemcpyHostToDevice));
+    FIO_HIP_TRY(hipMemcpy(d_off, off.data(), sizeof(long long) * nbins, hipMemcpyHostToDevice));
+    FIO_HIP_TRY(hipMemset(d_cnt, 0, sizeof(unsigned) * std::max<long long>(1, nbins)));
+    k_adj_bins<<<grid, 256>>>(P->phase, N, P->d_wedges, P->w, P->d_adj_ref, d_wbase, d_nb2, 1, d_cnt, d_off,
+                              P->d_adj_pts);
+    FIO_HIP_TRY(hipGetLastError());
+    FIO_HIP_TRY(hipDeviceSynchronize());
+    P->n_adj_bins = (int)nbins;
+    P->n_adj_pts = total;
+    return FIO_OK;
 }
 
 template <typename T, int... Ws>
@@ -423,12 +571,8 @@ static hipError_t adjoint_t(fio_plan_s *P, int B, const void *g, void *hhat, hip
     }
     for (int b0 = 0; b0 < B; b0 += P->bchunk) {
         const int bc = std::min(P->bchunk, B - b0);
-        e = zero_fill(P->d_G, sizeof(cplx<T>) * P->G_total * bc, s);
-        if (e != hipSuccess)
-            return e;
-        for (int bs = 0; bs < bc; bs += kInterpBatch) {
-            const int nb = std::min(kInterpBatch, bc - bs);
-            e = launch_spread<T>(P, a, gin + (b0 + bs) * NN, NN, nb, bs, s);
+        if (P->n_adj_bins > 0) {
+            e = launch_spread<T>(P, a, gin + b0 * NN, NN, bc, s);
             if (e != hipSuccess)
                 return e;
         }
@@ -447,14 +591,16 @@ static hipError_t adjoint_t(fio_plan_s *P, int B, const void *g, void *hhat, hip
     return hipSuccess;
 }
 
-hipError_t adjoint_launch(fio_plan_s *P, int B, const void *g, void *hhat, hipStream_t s) {
+fio_status adjoint_launch(fio_plan_s *P, int B, const void *g, void *hhat, hipStream_t s) {
     if (!P->adjoint_ready) {
-        const hipError_t e = adjoint_prepare(P);
-        if (e != hipSuccess)
-            return e;
+        FIO_HIP_TRY(adjoint_prepare(P));
+        const fio_status st = build_adj_bins(P);
+        if (st != FIO_OK)
+            return st;
         P->adjoint_ready = true;
     }
-    return P->precision == FIO_F64 ? adjoint_t<double>(P, B, g, hhat, s) : adjoint_t<float>(P, B, g, hhat, s);
+    FIO_HIP_TRY(P->precision == FIO_F64 ? adjoint_t<double>(P, B, g, hhat, s) : adjoint_t<float>(P, B, g, hhat, s));
+    return FIO_OK;
 }
 
 }  // namespace fio

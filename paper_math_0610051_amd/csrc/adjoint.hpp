@@ -7,7 +7,8 @@
 namespace fio {
 
 // hhat = L* g for B right-hand sides (g: B row-major grids, hhat: B centred
-// frequency arrays), stream-ordered on s; uses the plan's workspace.
-hipError_t adjoint_launch(fio_plan_s *P, int B, const void *g, void *hhat, hipStream_t s);
+// frequency arrays), stream-ordered on s; uses the plan's workspace.  The
+// first call on a plan builds its spreading blocks (synchronously).
+fio_status adjoint_launch(fio_plan_s *P, int B, const void *g, void *hhat, hipStream_t s);
 
 }  // namespace fio

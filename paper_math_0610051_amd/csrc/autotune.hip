@@ -148,12 +148,12 @@ fio_status probe_error(fio_plan_s *P, const void *fhat, const void *u, int ns, u
 
 // Cache key: everything a choice depends on, including the library build
 // (a cached choice of an older kernel build is not reused).
-static std::string tune_key(int N, const fio_phase *ph, double tol, const fio_options &o, int B) {
+static std::string tune_key(int N, const fio_phase *ph, int amp, double tol, const fio_options &o, int B) {
     char buf[512];
     std::snprintf(buf, sizeof(buf),
-                  "N=%d kind=%d p=%.9g,%.9g,%.9g tol=%.3g prec=%d part=%d mode=%d seed=%llu B=%d build=%s", N,
-                  ph->kind, ph->p[0], ph->p[1], ph->p[2], tol, o.precision, o.partition, o.factor_mode, o.seed, B,
-                  fio_version());
+                  "N=%d kind=%d p=%.9g,%.9g,%.9g amp=%d tol=%.3g prec=%d part=%d mode=%d seed=%llu B=%d build=%s",
+                  N, ph->kind, ph->p[0], ph->p[1], ph->p[2], amp, tol, o.precision, o.partition, o.factor_mode,
+                  o.seed, B, fio_version());
     return buf;
 }
 
@@ -241,7 +241,7 @@ fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp,
     else
         fio_default_options(&o);
     const char *cache = std::getenv("FIO_TUNE_CACHE");
-    const std::string key = tune_key(N, phase, tol, o, B);
+    const std::string key = tune_key(N, phase, amp ? amp->kind : FIO_AMP_ONE, tol, o, B);
     if (ntried)
         *ntried = 0;
     if (cache_lookup(cache, key, best))
@@ -257,7 +257,8 @@ fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp,
     for (int L : {L0, L0 + 8, L0 + 16})
         Ls.push_back(L);
     const double splits[][2] = {{0.25, 0.1}, {0.4, 0.15}};
-    const double sigmas[] = {2.0, 2.5};
+    // oversampling: below 2 the grids (and FFT stages) shrink while the kernel widens
+    const double sigmas[] = {1.5, 1.75, 2.0, 2.5};
     const size_t es = o.precision == FIO_F64 ? 16 : 8;
     const long long NN = (long long)N * N;
     void *d_f = nullptr, *d_u = nullptr;
@@ -336,7 +337,7 @@ fio_status fio_autotune(int N, const fio_phase *phase, const fio_amplitude *amp,
                 }
                 r.ms_per_rhs = ms / (3.0 * B);
                 double err = 1;
-                st = probe_error(P, d_f, d_u, 96, 0x5EEDull + count, &err, 0);
+                st = probe_error(P, d_f, d_u, 256, 0x5EEDull + count, &err, 0);
                 fio_destroy(P);
                 if (st != FIO_OK) {
                     result = st;

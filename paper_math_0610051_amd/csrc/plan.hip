@@ -781,7 +781,8 @@ void release_layout(fio_plan_s *P) {
     void **bufs[] = {(void **)&P->d_wedges, (void **)&P->d_fftplans, (void **)&P->d_rows, (void **)&P->d_cols,
                      (void **)&P->d_map,    (void **)&P->d_omega,    &P->d_gxi,             &P->d_gx,
                      &P->d_tw,              &P->d_H,                 &P->d_G,               &P->d_zcol,
-                     &P->d_zmat};
+                     &P->d_zmat,            (void **)&P->d_adj_bins, (void **)&P->d_adj_pts,
+                     (void **)&P->d_adj_ref};
     for (void **b : bufs) {
         if (*b)
             (void)hipFree(*b);
@@ -790,6 +791,9 @@ void release_layout(fio_plan_s *P) {
     P->rows.clear();
     P->cols.clear();
     P->wdev.clear();
+    P->n_adj_bins = 0;
+    P->n_adj_pts = 0;
+    P->adjoint_ready = false;
 }
 
 // Offsets, work items, device tables, factor storage and workspace for the

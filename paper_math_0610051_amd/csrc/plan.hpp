@@ -40,6 +40,13 @@ struct WedgeDev {
     int zrc, pad2;       // number of sampled columns (0 when gamma^x is stored)
 };
 
+// One block of an oversampled grid for the adjoint's spreading: wedge l,
+// first cell (o1, o2), and its n points at pts[off ...].
+struct AdjBin {
+    int l, o1, o2, n;
+    long long off;
+};
+
 // Work items of the two FFT stages.
 struct RowItem {   // stage 1: box rows [k1, k1 + nr) of wedge ell, ranks [t0, t0 + tn)
     int l, k1, nr, t0, tn, pad;
@@ -130,7 +137,15 @@ struct fio_plan_s {
     // rows of the row/column work tables restricted to a wedge range are
     // found by scanning: rows and cols are sorted by wedge.
     std::vector<int> row_first, col_first;   // L+1 prefix offsets
-    bool adjoint_ready = false;  // LDS limits of the adjoint kernels set
+    bool adjoint_ready = false;  // LDS limits of the adjoint kernels set, spreading bins built
+    // Spreading bins of the adjoint: every wedge's oversampled grid cut into
+    // kBin1 x kBin2 cell blocks, each with the grid points whose stencil
+    // touches it (built at the first adjoint apply)
+    fio::AdjBin *d_adj_bins = nullptr;
+    int *d_adj_pts = nullptr;
+    int2 *d_adj_ref = nullptr;  // integer reference of every output tile and wedge
+    int n_adj_bins = 0;
+    long long n_adj_pts = 0;
     // optional per-stage event timing
     int profiling = 0;
     struct StageEvents {
