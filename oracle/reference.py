@@ -322,6 +322,95 @@ def randomized_separation(N, kind, p, theta, k1, k2, eps, rng, r0=48, accept=1.0
     return dict(U=U, T=T, q=q, r=r, C=C, R=R, s=s)
 
 
+# --------------------------------------------------------------------------
+# Deterministic preprocessing (Section 3.1): Taylor expansions and
+# QR + SVD compression of products of separated expansions
+# --------------------------------------------------------------------------
+def angular_residual(kind, p, x1, x2, theta, theta_l):
+    """phi_ell(x, theta) = Phi_ell(x, xi) / |xi| for xi = |xi| (cos theta, sin theta):
+    h(x, e(theta)) - grad_xi h(x, e(theta_l)) . e(theta), valid for complex theta."""
+    e1, e2 = np.cos(theta), np.sin(theta)
+    g1, g2 = grad_h(kind, p, x1, x2, math.cos(theta_l), math.sin(theta_l))
+    a, b = _coeffs(kind, np.asarray(p, float), x1, x2) if kind != 0 else (None, None)
+    if kind == 0:
+        hv = p[0] * e1 + p[1] * e2
+    elif kind in (1, 3, 5):
+        hv = a * np.sqrt(e1 * e1 + e2 * e2 + 0j)
+    else:
+        hv = p[0] * np.sqrt(a * a * e1 * e1 + b * b * e2 * e2 + 0j)
+    return hv - (g1 * e1 + g2 * e2)
+
+
+def taylor_coefficients(kind, p, x1, x2, theta_l, K, radius=0.25, M=64):
+    """c_k(x), k = 0..K, of phi_ell(x, theta_l + t) = sum_k c_k t^k: the Cauchy
+    integral of phi_ell over a circle of the given radius around theta_l,
+    evaluated by the trapezoidal rule at M points (exact for the analytic
+    phi to about (radius / R)^M, R the distance to its nearest singularity).
+    Returns (len(x), K + 1)."""
+    z = radius * np.exp(2j * np.pi * np.arange(M) / M)
+    vals = angular_residual(kind, p, np.asarray(x1)[:, None], np.asarray(x2)[:, None], theta_l + z[None, :], theta_l)
+    coef = np.fft.fft(vals, axis=1) / M
+    k = np.arange(K + 1)
+    return (coef[:, :K + 1] / radius ** k[None, :]).real
+
+
+def _compress(X, Y, eps):
+    """X Y ~ X~ Y~ with fewer columns: QR of X and of Y^T, SVD of R_X R_Y^T,
+    singular values below eps * s_1 dropped (Section 3.1's compression)."""
+    QX, RX = np.linalg.qr(X)
+    QY, RY = np.linalg.qr(Y.T)
+    U, S, Vh = np.linalg.svd(RX @ RY.T)
+    q = max(1, int(np.count_nonzero(S > eps * S[0])))
+    return QX @ (U[:, :q] * S[:q]), Vh[:q] @ QY.T
+
+
+def taylor_separation(N, kind, p, theta_l, k1, k2, eps, pdeg=3, xidx=None):
+    """Deterministic separated approximation of A = exp(2 pi i Phi_ell) on
+    X x W_ell (Section 3.1), in the paper's steps:
+      1. Phi_ell(x, xi) ~ |xi| sum_{k=1}^{2p+1} c_k(x) (theta - theta_ell)^k;
+      2. for each k, exp(2 pi i c_k(x) |xi| (theta - theta_ell)^k) ~
+         sum_{m < d_k} beta^x_km(x) beta^xi_km(xi) by truncating the Taylor
+         series of the exponential (d_k: the first m with z^m / m! below
+         eps / 10, z the largest |2 pi c_k(x) |xi| (theta - theta_ell)^k|);
+      3. the expansions are multiplied two by two and each product is
+         compressed (QR and SVD, threshold eps relative to the largest
+         singular value).
+    Returns dict(X (n_x x q), Y (q x n_xi), q, ranks per product)."""
+    if xidx is None:
+        xidx = np.arange(N * N)
+    x1, x2 = x_of_index(N, xidx)
+    k1 = np.asarray(k1, float)
+    k2 = np.asarray(k2, float)
+    rad = np.sqrt(k1 * k1 + k2 * k2)
+    th = np.arctan2(k2, k1)
+    dth = np.angle(np.exp(1j * (th - theta_l)))
+    K = 2 * pdeg + 1
+    c = taylor_coefficients(kind, p, x1, x2, theta_l, K)
+    X = np.ones((x1.size, 1), complex)
+    Y = np.ones((1, k1.size), complex)
+    ranks = []
+    for k in range(1, K + 1):
+        tk = rad * dth ** k                      # |xi| (theta - theta_ell)^k
+        scale = max(np.max(np.abs(tk)), 1e-300)
+        zx = 2j * np.pi * c[:, k] * scale        # so that beta^xi = (tk / scale)^m is at most 1
+        zmax = np.max(np.abs(zx))
+        d = 1
+        term = 1.0
+        while term > eps / 10 and d < 200:
+            term *= zmax / d
+            d += 1
+        m = np.arange(d)
+        fact = np.array([math.factorial(int(v)) for v in m], float)
+        Bx = zx[:, None] ** m[None, :] / fact[None, :]
+        Bxi = (tk / scale)[None, :] ** m[:, None]
+        # product with the running expansion, then compression
+        Xp = (X[:, :, None] * Bx[:, None, :]).reshape(x1.size, -1)
+        Yp = (Y[:, None, :] * Bxi[None, :, :]).reshape(-1, k1.size)
+        X, Y = _compress(Xp, Yp, eps)
+        ranks.append(X.shape[1])
+    return dict(X=X, Y=Y, q=X.shape[1], ranks=ranks)
+
+
 def separation_error(N, kind, p, theta, k1, k2, U, T, rng, s=200):
     """Estimator of Section 4: ||A_GD - U_G T_D||_F / ||A_GD||_F on random s x s."""
     m = N * N
