@@ -193,11 +193,13 @@ fio_status fio_apply_batch(fio_plan_t plan, int B, const void *fhat, void *u, vo
  * DFT of hhat gives (L*g)(x).  It uses the plan's workspace, so a plan runs
  * one forward or adjoint apply at a time.  B right-hand sides are back to
  * back, as in fio_apply_batch.  The first adjoint call on a plan also lists,
- * for every block of each wedge's grid, the grid points whose stencils touch
- * it (about 8.4 bytes per grid point and wedge of device memory, owned by the
- * plan); that call synchronises the device.  The sums of the spreading are
- * formed with floating-point atomics, so the last bits can differ between
- * runs. */
+ * for every 4 x 8 cell strip of each wedge's grid, the grid points whose
+ * stencils touch it, in point order (about 12 bytes per grid point and wedge
+ * of device memory at kernel width 5, owned by the plan); that call
+ * synchronises the device.  The spreading sums every cell in list order;
+ * only where a wedge's transformed rows are split into chunks of ranks are
+ * the chunks added with floating-point atomics, so the last bits of such
+ * plans can differ between runs. */
 fio_status fio_apply_adjoint(fio_plan_t plan, const void *g, void *hhat, void *stream);
 fio_status fio_apply_adjoint_batch(fio_plan_t plan, int B, const void *g, void *hhat, void *stream);
 

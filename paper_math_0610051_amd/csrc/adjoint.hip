@@ -25,6 +25,8 @@
 #include <algorithm>
 #include <cstring>
 
+#include <rocprim/device/device_segmented_radix_sort.hpp>
+
 #include "adjoint.hpp"
 #include "apply.hpp"
 #include "errors.hpp"
@@ -39,33 +41,30 @@ __device__ __forceinline__ cplx<T> cconj(cplx<T> a) {
 }
 
 template <typename T>
-__device__ __forceinline__ void lds_add(T *p, T v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);  // ds_add_f32 / ds_add_f64
-}
-
-template <typename T>
 __device__ __forceinline__ void global_add(T *p, T v) {
     unsafeAtomicAdd(p, v);  // hardware global_atomic_add_f32 / _f64
 }
 
 // ---------------------------------------------------------------------------
-// Stage A1: spreading, gathered per block of the oversampled grid.  Each
-// wedge's grid is cut into kBin1 x kBin2 cell blocks; at the first adjoint
-// apply every grid point x is listed in the blocks its w x w stencil touches
-// (a point's warp and stencil do not depend on the input).  A workgroup owns
-// one block: it accumulates conj(gamma^x_t(x)) conj(exp(2 pi i psi(x))) g_b(x)
-// times the ES weights of the taps that fall in the block, for every listed
-// point and every plane (b, t), in LDS (float atomics: several points hit a
-// cell), and writes the block once with plain stores.  Every grid cell
-// belongs to exactly one block, so the grids need no clearing and no global
-// atomics are involved.
+// Stage A1: spreading, gathered per strip of the oversampled grid.  Each
+// wedge's grid is cut into strips of kStripRows<T> x kStripCols cells; at the
+// first adjoint apply every grid point x is listed in the strips its w x w
+// stencil touches (a point's warp and stencil do not depend on the input).
+// One wave owns one strip and keeps its cells in registers: lane k carries
+// plane k (RHS b, rank t) of every cell, and for each listed point it adds
+// conj(gamma^x_t(x)) conj(exp(2 pi i psi(x))) g_b(x) times the ES weight of
+// each tap row and column that falls in the strip (zero elsewhere).  The
+// FP64 warp, stencil and weights of 64 listed points are formed lane-parallel
+// and broadcast with readlane, and the next point's factor and input values
+// are fetched while the current one is added.  Every grid cell belongs to
+// exactly one strip, which writes it once: the grids need no clearing, and
+// neither LDS nor global atomics are involved.
 // ---------------------------------------------------------------------------
-constexpr int kBin1 = 16, kBin2 = 8;  // block of cells along the long (1) and short (2) grid axes
-constexpr int kBinCells = kBin1 * kBin2;
 template <typename T>
-constexpr int kSpreadPlanes = sizeof(T) == 4 ? 32 : 16;  // (RHS, rank) planes per round
-template <typename T>
-constexpr int kSpreadLds = kBinCells * (2 * kSpreadPlanes<T> + 1) * (int)sizeof(T);
+constexpr int kStripRows = 4;  // cells along the long grid axis (1)
+constexpr int kStripCols = 8;  // cells along the short grid axis (2)
+constexpr int kSpreadLanes = 64;                     // planes per round: one per lane
+constexpr int kSpreadMaxB = 16;                      // right-hand sides per round
 
 // Warped point of x in wedge W, its stencil's first cell on each axis
 // wrapped into [0, m), and the fractions f = u - j of the unwrapped grid
@@ -143,7 +142,7 @@ __device__ inline int2 tile_ref(const int2 *ref, int N, int l, int n1, int n2) {
     return ref[(long long)l * tiles * tiles + (n1 / kTileX) * tiles + n2 / kTileX];
 }
 
-// Distinct blocks (at most 4 per axis) that the W cells j, j+1, ... (mod m) touch.
+// Distinct strips (at most w per axis) that the w cells j, j+1, ... (mod m) touch.
 __device__ inline int stencil_bins(int j, int W, int m, int bb, int *bins) {
     int n = 0, last = -1;
     for (int i = 0; i < W; ++i) {
@@ -161,7 +160,7 @@ __device__ inline int stencil_bins(int j, int W, int m, int bb, int *bins) {
 
 // Bin builder, pass 0 counts and pass 1 fills: thread = (grid point, wedge).
 __global__ void k_adj_bins(Phase ph, int N, const WedgeDev *__restrict__ wedges, int W, const int2 *__restrict__ ref,
-                           const long long *__restrict__ wbase, const int *__restrict__ nb2, int pass,
+                           int bb1, int bb2, const long long *__restrict__ wbase, const int *__restrict__ nb2, int pass,
                            unsigned *__restrict__ counter, const long long *__restrict__ off, int *__restrict__ pts) {
     const long long NN = (long long)N * N;
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -176,8 +175,8 @@ __global__ void k_adj_bins(Phase ph, int N, const WedgeDev *__restrict__ wedges,
     const XCoef c = phase_xcoef(ph, x1, x2);
     double g1, g2;
     const SpreadPoint sp = spread_point(ph, wd, x1, x2, c, W, tile_ref(ref, N, l, n1, n2), g1, g2);
-    int b1[4], b2[4];
-    const int k1 = stencil_bins(sp.j1, W, wd.n1, kBin1, b1), k2 = stencil_bins(sp.j2, W, wd.n2, kBin2, b2);
+    int b1[16], b2[16];
+    const int k1 = stencil_bins(sp.j1, W, wd.n1, bb1, b1), k2 = stencil_bins(sp.j2, W, wd.n2, bb2, b2);
     for (int a = 0; a < k1; ++a)
         for (int b = 0; b < k2; ++b) {
             const long long bin = wbase[l] + (long long)b1[a] * nb2[l] + b2[b];
@@ -187,129 +186,173 @@ __global__ void k_adj_bins(Phase ph, int N, const WedgeDev *__restrict__ wedges,
         }
 }
 
+__device__ __forceinline__ int lane_bcast(int v, int k) { return __builtin_amdgcn_readlane(v, k); }
+__device__ __forceinline__ float lane_bcast(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ double lane_bcast(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k), hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 template <typename T, int W, bool REGEN>
-__global__ __launch_bounds__(kThreads) void k_spread(PlanArgs<T> a, const AdjBin *__restrict__ bins,
+__global__ __launch_bounds__(kThreads) void k_spread(PlanArgs<T> a, const AdjBin *__restrict__ bins, int nbins,
                                                      const int *__restrict__ pts, const int2 *__restrict__ ref,
                                                      const cplx<T> *__restrict__ g, long long gstride, int B,
-                                                     int bofs) {
+                                                     int bofs, int qstage) {
+    constexpr int R = kStripRows<T>, C = kStripCols;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int bi = blockIdx.x * (kThreads / 64) + wave;
+    if (bi >= nbins)
+        return;  // waves are independent: no barrier below
     extern __shared__ unsigned char smem_raw[];
-    // [cell][plane of the round][re, im] with an odd cell stride of 2 kPlanes + 1
-    // words, so that the cells of one plane fall in different LDS banks
-    T *win = reinterpret_cast<T *>(smem_raw);
-    constexpr int kPlanes = kSpreadPlanes<T>;
-    constexpr int kCellStride = 2 * kPlanes + 1;
-    const AdjBin bin = bins[blockIdx.x];
+    // FIO_FACTORS_REGEN: gamma^x of the wave's 64 staged points, [point][rank]
+    cplx<T> *sgx = reinterpret_cast<cplx<T> *>(smem_raw) + (size_t)wave * 64 * qstage;
+    const AdjBin bin = bins[bi];
     const WedgeDev &wd = a.wedges[bin.l];
-    const int N = a.N, m1 = wd.n1, m2 = wd.n2, q = wd.q, tid = threadIdx.x;
-    const int nplanes = B * q;
+    const int N = a.N, m1 = wd.n1, m2 = wd.n2, q = wd.q;
     cplx<T> *G0 = a.G + (long long)bofs * a.G_stride + wd.G_off;
     const cplx<T> *gx0 = a.gx + wd.gx_off;
-    // a stride prime to the list length visits every entry once
-    const int stride = bin.n % 7919 ? 7919 : (bin.n % 7927 ? 7927 : 1);
-    for (int p0 = 0; p0 < nplanes; p0 += kPlanes) {
-        const int np = min(kPlanes, nplanes - p0);
-        for (int e = tid; e < kBinCells * kCellStride; e += kThreads)
-            win[e] = T(0);
-        __syncthreads();
-        for (int k = tid; k < bin.n; k += kThreads) {
-            // The list runs in point order, and neighbouring points share
-            // stencil cells: lanes take entries a prime stride apart, so that
-            // the lanes of one LDS atomic hit different cells.
-            const int p = pts[bin.off + (int)(((long long)k * stride) % bin.n)];
-            const int n1 = p / N, n2 = p - n1 * N;
-            const double x1 = (double)n1 / N, x2 = (double)n2 / N;
-            const XCoef c = phase_xcoef(a.phase, x1, x2);
-            double g1, g2;
-            const SpreadPoint sp = spread_point(a.phase, wd, x1, x2, c, W, tile_ref(ref, N, bin.l, n1, n2), g1, g2);
-            double psi = wd.cvec[0] * sp.y1 + wd.cvec[1] * sp.y2;
-            psi -= rint(psi);
-            T cs, sn;
-            expi_t<T>(psi, cs, sn);
-            const cplx<T> cmod = cmake<T>(cs, -sn);  // conj(exp(2 pi i psi))
-            const T f1 = (T)sp.f1, f2 = (T)sp.f2;
-            // taps inside this block: rows r0 + i1 in [0, kBin1), columns c0 + i2 in [0, kBin2)
-            int r0 = sp.j1 - bin.o1, c0 = sp.j2 - bin.o2;
-            if (r0 < -W)
-                r0 += m1;
-            else if (r0 >= kBin1)
-                r0 -= m1;
-            if (c0 < -W)
-                c0 += m2;
-            else if (c0 >= kBin2)
-                c0 -= m2;
-            T w1[W], w2[W];
+    for (int t0 = 0; t0 < q; t0 += kSpreadLanes) {
+        const int tn = min(kSpreadLanes, q - t0);
+        const int bmax = min(kSpreadMaxB, kSpreadLanes / tn);
+        for (int b0 = 0; b0 < B; b0 += bmax) {
+            const int nb = min(bmax, B - b0);
+            // this lane's plane: RHS b0 + bl, rank t0 + tl (lanes past nb tn compute a copy of a live plane)
+            const int bl = min(lane / tn, nb - 1), tl = lane % tn;
+            const cplx<T> *gb = g + (long long)(b0 + bl) * gstride;
+            cplx<T> acc[R][C];
 #pragma unroll
-            for (int i = 0; i < W; ++i) {
-                w1[i] = (r0 + i >= 0 && r0 + i < kBin1) ? es_weight<T>(f1 - T(i), a.two_over_w, a.beta) : T(0);
-                w2[i] = (c0 + i >= 0 && c0 + i < kBin2) ? es_weight<T>(f2 - T(i), a.two_over_w, a.beta) : T(0);
-            }
-            cplx<T> gxr[REGEN ? kRegenMaxRank : 1];
-            if constexpr (REGEN) {
-                const double2 *zc = a.zcol + wd.zc_off;
-                const double2 *zm = a.zmat + wd.zm_off;
-                double ar[kRegenMaxRank], ai[kRegenMaxRank];
+            for (int j = 0; j < R; ++j)
 #pragma unroll
-                for (int t = 0; t < kRegenMaxRank; ++t)
-                    ar[t] = ai[t] = 0;
-                for (int cc = 0; cc < wd.zrc; ++cc) {
-                    const double2 kk = zc[cc];
-                    double cs2, sn2;
-                    residual_entry(a.phase, c, g1, g2, kk.x, kk.y, cs2, sn2);
-                    const double2 *zr = zm + (long long)cc * q;
+                for (int c = 0; c < C; ++c)
+                    acc[j][c] = cmake<T>(0, 0);
+            for (int kb = 0; kb < bin.n; kb += 64) {
+                const int nbt = min(64, bin.n - kb);
+                // lane i forms the record of listed point kb + i
+                int p = 0, r0 = 0;
+                T wr[R], wc[C];
+                cplx<T> md = cmake<T>(0, 0);
 #pragma unroll
-                    for (int t = 0; t < kRegenMaxRank; ++t)
-                        if (t < q) {
-                            const double2 z = zr[t];
-                            ar[t] += cs2 * z.x - sn2 * z.y;
-                            ai[t] += cs2 * z.y + sn2 * z.x;
+                for (int j = 0; j < R; ++j)
+                    wr[j] = T(0);
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    wc[c] = T(0);
+                if (lane < nbt) {
+                    p = pts[bin.off + kb + lane];
+                    const int n1 = p / N, n2 = p - n1 * N;
+                    const double x1 = (double)n1 / N, x2 = (double)n2 / N;
+                    const XCoef c = phase_xcoef(a.phase, x1, x2);
+                    double g1, g2;
+                    const SpreadPoint sp =
+                        spread_point(a.phase, wd, x1, x2, c, W, tile_ref(ref, N, bin.l, n1, n2), g1, g2);
+                    double psi = wd.cvec[0] * sp.y1 + wd.cvec[1] * sp.y2;
+                    psi -= rint(psi);
+                    T cs, sn;
+                    expi_t<T>(psi, cs, sn);
+                    md = cmake<T>(cs, -sn);
+                    // first stencil cell relative to the strip, wrapped next to it
+                    r0 = sp.j1 - bin.o1;
+                    int c0 = sp.j2 - bin.o2;
+                    if (r0 < -W)
+                        r0 += m1;
+                    else if (r0 >= R)
+                        r0 -= m1;
+                    if (c0 < -W)
+                        c0 += m2;
+                    else if (c0 >= C)
+                        c0 -= m2;
+                    const T f1 = (T)sp.f1, f2 = (T)sp.f2;
+#pragma unroll
+                    for (int j = 0; j < R; ++j) {
+                        const int k = j - r0;
+                        wr[j] = k >= 0 && k < W ? es_weight<T>(f1 - T(k), a.two_over_w, a.beta) : T(0);
+                    }
+#pragma unroll
+                    for (int cc = 0; cc < C; ++cc) {
+                        const int k = cc - c0;
+                        wc[cc] = k >= 0 && k < W ? es_weight<T>(f2 - T(k), a.two_over_w, a.beta) : T(0);
+                    }
+                    if constexpr (REGEN) {  // q <= kRegenMaxRank: one round of ranks
+                        const double2 *zc = a.zcol + wd.zc_off;
+                        const double2 *zm = a.zmat + wd.zm_off;
+                        double ar[kRegenMaxRank], ai[kRegenMaxRank];
+#pragma unroll
+                        for (int t = 0; t < kRegenMaxRank; ++t)
+                            ar[t] = ai[t] = 0;
+                        for (int cc = 0; cc < wd.zrc; ++cc) {
+                            const double2 kk = zc[cc];
+                            double cs2, sn2;
+                            residual_entry(a.phase, c, g1, g2, kk.x, kk.y, cs2, sn2);
+                            const double2 *zr = zm + (long long)cc * q;
+#pragma unroll
+                            for (int t = 0; t < kRegenMaxRank; ++t)
+                                if (t < q) {
+                                    const double2 z = zr[t];
+                                    ar[t] += cs2 * z.x - sn2 * z.y;
+                                    ai[t] += cs2 * z.y + sn2 * z.x;
+                                }
+                        }
+#pragma unroll
+                        for (int t = 0; t < kRegenMaxRank; ++t)
+                            if (t < q)
+                                sgx[lane * qstage + t] = cmake<T>((T)ar[t], (T)ai[t]);
+                    }
+                }
+                if constexpr (REGEN)
+                    __builtin_amdgcn_wave_barrier();  // the wave's LDS writes precede its reads (in-order LDS)
+                // point k of the batch: its factor and input values are loaded one point ahead
+                auto fetch = [&](int k, cplx<T> &x, cplx<T> &y) {
+                    const int pk = lane_bcast(p, k);
+                    if constexpr (REGEN)
+                        x = sgx[k * qstage + t0 + tl];
+                    else
+                        x = gx0[(long long)pk * q + t0 + tl];
+                    y = gb[pk];
+                };
+                cplx<T> nx, ny;
+                fetch(0, nx, ny);
+                for (int k = 0; k < nbt; ++k) {
+                    const cplx<T> cx = nx, cy = ny;
+                    if (k + 1 < nbt)
+                        fetch(k + 1, nx, ny);
+                    const int rk = lane_bcast(r0, k);
+                    const cplx<T> mk = cmake<T>(lane_bcast(md.re, k), lane_bcast(md.im, k));
+                    const cplx<T> v = cmul(cconj(cx), cmul(mk, cy));
+                    T wcol[C];
+#pragma unroll
+                    for (int cc = 0; cc < C; ++cc)
+                        wcol[cc] = lane_bcast(wc[cc], k);
+#pragma unroll
+                    for (int j = 0; j < R; ++j)
+                        if (j - rk >= 0 && j - rk < W) {  // a tap row of the point (uniform branch)
+                            const T w = lane_bcast(wr[j], k);
+                            const T ar = w * v.re, ai = w * v.im;
+#pragma unroll
+                            for (int cc = 0; cc < C; ++cc) {
+                                acc[j][cc].re += wcol[cc] * ar;
+                                acc[j][cc].im += wcol[cc] * ai;
+                            }
                         }
                 }
-#pragma unroll
-                for (int t = 0; t < kRegenMaxRank; ++t)
-                    gxr[t] = cmake<T>((T)ar[t], (T)ai[t]);
             }
-            for (int kp = 0; kp < np; ++kp) {
-                const int pl = p0 + kp, b = pl / q, t = pl - b * q;
-                cplx<T> gx;
-                if constexpr (REGEN) {
-                    gx = gxr[0];
+            // the strip's cells (G is [j2][j1][rank])
+            if (lane < nb * tn) {
 #pragma unroll
-                    for (int tt = 1; tt < kRegenMaxRank; ++tt)
-                        if (tt == t)
-                            gx = gxr[tt];
-                } else {
-                    gx = gx0[(long long)p * q + t];
-                }
-                const cplx<T> v = cmul(cconj(gx), cmul(cmod, g[b * gstride + p]));
+                for (int cc = 0; cc < C; ++cc) {
+                    const int gc = bin.o2 + cc;
 #pragma unroll
-                for (int i1 = 0; i1 < W; ++i1) {
-                    if (w1[i1] == T(0))
-                        continue;
-                    const T ar = w1[i1] * v.re, ai = w1[i1] * v.im;
-                    const int rowc = (r0 + i1) * kBin2;
-#pragma unroll
-                    for (int i2 = 0; i2 < W; ++i2)
-                        if (w2[i2] != T(0)) {
-                            T *cellp = win + (rowc + c0 + i2) * kCellStride + 2 * kp;
-                            lds_add(cellp, w2[i2] * ar);
-                            lds_add(cellp + 1, w2[i2] * ai);
-                        }
+                    for (int j = 0; j < R; ++j) {
+                        const int gr = bin.o1 + j;
+                        if (gr < m1 && gc < m2)
+                            G0[(long long)(b0 + bl) * a.G_stride + ((long long)gc * m1 + gr) * q + t0 + tl] =
+                                acc[j][cc];
+                    }
                 }
             }
         }
-        __syncthreads();
-        // the block's cells, all ranks of a cell together (G is [j2][j1][rank])
-        for (int e = tid; e < kBinCells * np; e += kThreads) {
-            const int cell = e / np, kp = e - cell * np;
-            const int rr = cell / kBin2, cc = cell - rr * kBin2;
-            const int gr = bin.o1 + rr, gc = bin.o2 + cc;
-            if (gr >= m1 || gc >= m2)
-                continue;
-            const int pl = p0 + kp, b = pl / q, t = pl - b * q;
-            const T *src = win + cell * kCellStride + 2 * kp;
-            G0[(long long)b * a.G_stride + ((long long)gc * m1 + gr) * q + t] = cmake<T>(src[0], src[1]);
-        }
-        __syncthreads();  // the window is cleared for the next round
     }
 }
 
@@ -421,12 +464,18 @@ __global__ __launch_bounds__(kFftThreads) void k_rows_adj(PlanArgs<T> a, const R
 template <typename T, int W>
 static hipError_t launch_spread_w(const fio_plan_s *P, const PlanArgs<T> &a, const cplx<T> *g, long long gstride,
                                   int B, hipStream_t s) {
-    if (P->regen)
-        k_spread<T, W, true><<<(unsigned)P->n_adj_bins, kThreads, kSpreadLds<T>, s>>>(
-            a, P->d_adj_bins, P->d_adj_pts, P->d_adj_ref, g, gstride, B, 0);
-    else
-        k_spread<T, W, false><<<(unsigned)P->n_adj_bins, kThreads, kSpreadLds<T>, s>>>(
-            a, P->d_adj_bins, P->d_adj_pts, P->d_adj_ref, g, gstride, B, 0);
+    const unsigned grid = (unsigned)((P->n_adj_bins + kThreads / 64 - 1) / (kThreads / 64));
+    if (P->regen) {
+        const int qstage = P->qmax;
+        const size_t lds = (size_t)(kThreads / 64) * 64 * qstage * sizeof(cplx<T>);
+        if (lds > (size_t)kMaxLdsBytes)
+            return hipErrorInvalidConfiguration;
+        k_spread<T, W, true><<<grid, kThreads, lds, s>>>(a, P->d_adj_bins, P->n_adj_bins, P->d_adj_pts, P->d_adj_ref,
+                                                        g, gstride, B, 0, qstage);
+    } else {
+        k_spread<T, W, false><<<grid, kThreads, 0, s>>>(a, P->d_adj_bins, P->n_adj_bins, P->d_adj_pts,
+                                                       P->d_adj_ref, g, gstride, B, 0, 0);
+    }
     return hipGetLastError();
 }
 
@@ -451,14 +500,15 @@ static hipError_t launch_spread(const fio_plan_s *P, const PlanArgs<T> &a, const
 // k_adj_bins: counts, then the lists at their exclusive prefix offsets).
 static fio_status build_adj_bins(fio_plan_s *P) {
     const int L = P->L, N = P->N;
+    const int bb1 = P->precision == FIO_F64 ? kStripRows<double> : kStripRows<float>, bb2 = kStripCols;
     const long long NN = (long long)N * N;
     std::vector<long long> wbase(L + 1, 0);
     std::vector<int> nb1(L, 0), nb2(L, 0);
     for (int l = 0; l < L; ++l) {
         const WedgeDev &wd = P->wdev[l];
         if (wd.q > 0) {
-            nb1[l] = (wd.n1 + kBin1 - 1) / kBin1;
-            nb2[l] = (wd.n2 + kBin2 - 1) / kBin2;
+            nb1[l] = (wd.n1 + bb1 - 1) / bb1;
+            nb2[l] = (wd.n2 + bb2 - 1) / bb2;
         }
         wbase[l + 1] = wbase[l] + (long long)nb1[l] * nb2[l];
     }
@@ -491,8 +541,8 @@ static fio_status build_adj_bins(fio_plan_s *P) {
     FIO_HIP_TRY(hipGetLastError());
     const dim3 grid((unsigned)((NN + 255) / 256), (unsigned)L);
     FIO_HIP_TRY(hipMemset(d_cnt, 0, sizeof(unsigned) * std::max<long long>(1, nbins)));
-    k_adj_bins<<<grid, 256>>>(P->phase, N, P->d_wedges, P->w, P->d_adj_ref, d_wbase, d_nb2, 0, d_cnt, nullptr,
-                              nullptr);
+    k_adj_bins<<<grid, 256>>>(P->phase, N, P->d_wedges, P->w, P->d_adj_ref, bb1, bb2, d_wbase, d_nb2, 0, d_cnt,
+                              nullptr, nullptr);
     FIO_HIP_TRY(hipGetLastError());
     std::vector<unsigned> cnt(nbins);
     FIO_HIP_TRY(hipMemcpy(cnt.data(), d_cnt, sizeof(unsigned) * nbins, hipMemcpyDeviceToHost));
@@ -507,16 +557,47 @@ static fio_status build_adj_bins(fio_plan_s *P) {
         for (int b1 = 0; b1 < nb1[l]; ++b1)
             for (int b2 = 0; b2 < nb2[l]; ++b2) {
                 const long long i = wbase[l] + (long long)b1 * nb2[l] + b2;
-                bins[i] = AdjBin{l, b1 * kBin1, b2 * kBin2, (int)cnt[i], off[i]};
+                bins[i] = AdjBin{l, b1 * bb1, b2 * bb2, (int)cnt[i], off[i]};
             }
     FIO_HIP_TRY(hipMalloc(&P->d_adj_pts, sizeof(int) * std::max<long long>(1, total)));
     FIO_HIP_TRY(hipMalloc(&P->d_adj_bins, sizeof(AdjBin) * std::max<long long>(1, nbins)));
     FIO_HIP_TRY(hipMemcpy(P->d_adj_bins, bins.data(), sizeof(AdjBin) * nbins, hipMemcpyHostToDevice));
     FIO_HIP_TRY(hipMemcpy(d_off, off.data(), sizeof(long long) * nbins, hipMemcpyHostToDevice));
     FIO_HIP_TRY(hipMemset(d_cnt, 0, sizeof(unsigned) * std::max<long long>(1, nbins)));
-    k_adj_bins<<<grid, 256>>>(P->phase, N, P->d_wedges, P->w, P->d_adj_ref, d_wbase, d_nb2, 1, d_cnt, d_off,
-                              P->d_adj_pts);
+    k_adj_bins<<<grid, 256>>>(P->phase, N, P->d_wedges, P->w, P->d_adj_ref, bb1, bb2, d_wbase, d_nb2, 1, d_cnt,
+                              d_off, P->d_adj_pts);
     FIO_HIP_TRY(hipGetLastError());
+    // Every list in point order (the fill above takes atomic slots): the
+    // spreading then sums each cell in a fixed order, so adjoint applies are
+    // reproducible bit for bit, and it walks gamma^x and g in memory order.
+    if (total > 1 && total < (1ll << 32) && nbins < (1ll << 32)) {
+        std::vector<unsigned> off32(nbins + 1);
+        for (long long i = 0; i < nbins; ++i)
+            off32[i] = (unsigned)off[i];
+        off32[nbins] = (unsigned)total;
+        unsigned *d_off32 = nullptr;
+        int *sorted = nullptr;
+        void *work = nullptr;
+        FIO_HIP_TRY(hipMalloc(&d_off32, sizeof(unsigned) * (nbins + 1)));
+        tmp.p.push_back(d_off32);
+        FIO_HIP_TRY(hipMemcpy(d_off32, off32.data(), sizeof(unsigned) * (nbins + 1), hipMemcpyHostToDevice));
+        FIO_HIP_TRY(hipMalloc(&sorted, sizeof(int) * total));
+        tmp.p.push_back(sorted);
+        const size_t slot = tmp.p.size() - 1;
+        unsigned bits = 1;
+        while ((1ll << bits) < NN)
+            ++bits;
+        size_t work_bytes = 0;
+        FIO_HIP_TRY(rocprim::segmented_radix_sort_keys(nullptr, work_bytes, P->d_adj_pts, sorted, (unsigned)total,
+                                                       (unsigned)nbins, d_off32, d_off32 + 1, 0, bits));
+        FIO_HIP_TRY(hipMalloc(&work, std::max<size_t>(work_bytes, 1)));
+        tmp.p.push_back(work);
+        FIO_HIP_TRY(rocprim::segmented_radix_sort_keys(work, work_bytes, P->d_adj_pts, sorted, (unsigned)total,
+                                                       (unsigned)nbins, d_off32, d_off32 + 1, 0, bits));
+        FIO_HIP_TRY(hipDeviceSynchronize());
+        tmp.p[slot] = P->d_adj_pts;  // the unsorted lists are freed with the temporaries
+        P->d_adj_pts = sorted;
+    }
     FIO_HIP_TRY(hipDeviceSynchronize());
     P->n_adj_bins = (int)nbins;
     P->n_adj_pts = total;

@@ -139,7 +139,7 @@ struct fio_plan_s {
     std::vector<int> row_first, col_first;   // L+1 prefix offsets
     bool adjoint_ready = false;  // LDS limits of the adjoint kernels set, spreading bins built
     // Spreading bins of the adjoint: every wedge's oversampled grid cut into
-    // kBin1 x kBin2 cell blocks, each with the grid points whose stencil
+    // blocks of cells, each with the grid points whose stencil
     // touches it (built at the first adjoint apply)
     fio::AdjBin *d_adj_bins = nullptr;
     int *d_adj_pts = nullptr;

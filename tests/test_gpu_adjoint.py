@@ -95,9 +95,9 @@ def test_adjoint_inverts_a_wave_multiplier():
 
 @pytest.mark.parametrize("mode", ["stored", "regen"])
 def test_adjoint_batch_and_factor_modes(mode):
-    """A batch of right-hand sides equals single applies to rounding (the
-    spreading adds with atomics, so the order of additions may differ), and
-    regenerated factors agree with stored ones."""
+    """A batch of right-hand sides equals single applies to rounding (rank
+    chunks of the row stage may be summed in another order), and regenerated
+    factors agree with stored ones."""
     N, B = 96, 3
     rng = np.random.default_rng(44)
     g = fi.complex_gaussian(N, rng, B=B)
