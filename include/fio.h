@@ -96,8 +96,22 @@ enum { FIO_PART_EQUIANGULAR = 0, FIO_PART_CORONAE = 1 };
  * gamma^x(x) = A(x, C) Z from the FP64 residual phase (Section 3.2, the
  * storage-compressed form): far less memory, more arithmetic per apply, and
  * available while the padded rank is at most 16 (FP32) or 8 (FP64);
- * LEARNED takes gamma^x from a trained network. */
-enum { FIO_FACTORS_AUTO = 0, FIO_FACTORS_STORED = 1, FIO_FACTORS_REGEN = 2, FIO_FACTORS_LEARNED = 3 };
+ * LEARNED takes gamma^x from a trained network; TAYLOR builds both factors by
+ * the deterministic preprocessing of Section 3.1 (polar Taylor expansion of
+ * the residual phase, truncated exponential series, QR and SVD compression
+ * of the products; FP64 on the GPU with rocBLAS), stored like STORED, for
+ * the amplitude a = 1 only (FIO_ENOTSUP otherwise); FIO_EACCURACY where a
+ * wedge reaches past the polar series' radius of convergence (the nearest
+ * complex singularity of the residual phase in the angle, about 0.11 rad for
+ * the paper's ellipse family) or the series needs more than 31 orders: more
+ * wedges then help.  Its plans are not written to plan files (FIO_ENOTSUP). */
+enum {
+    FIO_FACTORS_AUTO = 0,
+    FIO_FACTORS_STORED = 1,
+    FIO_FACTORS_REGEN = 2,
+    FIO_FACTORS_LEARNED = 3,
+    FIO_FACTORS_TAYLOR = 4
+};
 
 /* Plan options.  Start from fio_default_options(); zero means "automatic" where noted. */
 typedef struct {
@@ -108,7 +122,8 @@ typedef struct {
                                network of the same N is given, else L ~ sqrt(N) (Section 1.3) raised for
                                strong phases: the multiple of 8 at least 8 ceil(sqrt(N) / 8) and
                                pi sqrt(S N / (1.5 sqrt 2)), S = max |grad_xi h| of the family */
-    int factor_mode;        /* FIO_FACTORS_AUTO / STORED / REGEN (exact separation) / LEARNED (network) */
+    int factor_mode;        /* FIO_FACTORS_AUTO / STORED / REGEN (randomized separation) / LEARNED (network) /
+                               TAYLOR (deterministic expansion) */
     unsigned long long seed;/* seed of the column/row sampling of the separation */
     int max_batch;          /* right-hand sides processed per pass of the workspace (default 8) */
     double sep_tol_frac;    /* separation threshold = tol * sep_tol_frac (default 0.25) */

@@ -19,7 +19,8 @@ OUT_DIR = os.path.join(HERE, "_lib")
 OBJ_DIR = os.path.join(OUT_DIR, "obj")
 LIB_PATH = os.path.join(OUT_DIR, "libfio.so")
 
-HIP_SOURCES = ["abi.hip", "plan.hip", "apply.hip", "adjoint.hip", "multi.hip", "learned.hip", "autotune.hip"]
+HIP_SOURCES = ["abi.hip", "plan.hip", "apply.hip", "adjoint.hip", "multi.hip", "learned.hip", "autotune.hip",
+               "taylor.hip"]
 CXX_SOURCES = ["linalg.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -29,6 +30,7 @@ HIP_FLAGS = [
     "-Wno-unused-result", "-Wno-unused-command-line-argument",
 ]
 CXX_FLAGS = ["-O2", "-fPIC", "-std=c++17"]
+LINK_LIBS = ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]  # rocBLAS: the Taylor factors' Gram and product GEMMs
 
 
 def _run(cmd):
@@ -71,7 +73,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
             if verbose and out.strip():
                 sys.stdout.write(out)
     tmp = LIB_PATH + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + LINK_LIBS)
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
 

@@ -154,7 +154,7 @@ fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, 
     // 1e-7 of the largest (its threshold is tol * sep_tol_frac)
     if (tol < 5e-7)
         return (set_error("tol below the floor (5e-7) of the Gram-matrix separation"), FIO_ENOTSUP);
-    if (o.factor_mode < FIO_FACTORS_AUTO || o.factor_mode > FIO_FACTORS_LEARNED)
+    if (o.factor_mode < FIO_FACTORS_AUTO || o.factor_mode > FIO_FACTORS_TAYLOR)
         return (set_error("unknown factor mode"), FIO_EINVAL);
     if (o.factor_mode == FIO_FACTORS_LEARNED && !o.learned)
         return (set_error("FIO_FACTORS_LEARNED needs a trained network"), FIO_EINVAL);

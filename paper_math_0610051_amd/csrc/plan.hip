@@ -421,6 +421,9 @@ template std::vector<int> sample_distinct<int>(int, int, uint64_t &);
 template std::vector<long long> sample_distinct<long long>(long long, int, uint64_t &);
 
 std::vector<int> sample_members(int n, int k, uint64_t &state) { return sample_distinct<int>(n, k, state); }
+std::vector<long long> sample_points(long long n, int k, uint64_t &state) {
+    return sample_distinct<long long>(n, k, state);
+}
 
 // Gram matrix A_C^H A_C (r x r, full Hermitian) of the residual kernel columns
 // at frequencies `cols` over every grid point, reduced on the GPU in FP64.
@@ -604,6 +607,20 @@ DeviceScratch::~DeviceScratch() {
 // ---------------------------------------------------------------------------
 // Device storage of factors, tables and workspace
 // ---------------------------------------------------------------------------
+// Factor folded into gamma^xi of every member: the kernel's deconvolution
+// 1 / phi_hat along both axes of the sheared box, and 1/N.
+std::vector<double> member_scale(int N, const WedgeHost &W) {
+    const int h = N / 2;
+    std::vector<double> scale(W.members.size());
+    for (size_t m = 0; m < W.members.size(); ++m) {
+        const int om = W.members[m];
+        const int k1 = om / N - h, k2 = om % N - h;
+        const int a1 = W.M[0] * k1 + W.M[1] * k2 - W.xc[0], a2 = W.M[2] * k1 + W.M[3] * k2 - W.xc[1];
+        scale[m] = W.dec1[a1 - W.lo[0]] * W.dec2[a2 - W.lo[1]] / N;
+    }
+    return scale;
+}
+
 // gamma^xi = scale * (P A_[R]) for every member (and gamma^x = A_[C] Z for
 // every grid point when exact_x), evaluated in FP64 and stored as T.
 template <typename T>
@@ -680,13 +697,7 @@ static fio_status store_factors(fio_plan_s *P, const double2 *d_xcoef, bool exac
             phase_grad(P->phase, c, e1, e2, g1, g2);
             rows[i] = make_double4(c.a, c.b, g1, g2);
         }
-        std::vector<double> scale(W.members.size());
-        for (size_t m = 0; m < W.members.size(); ++m) {
-            const int om = W.members[m];
-            const int k1 = om / N - h, k2 = om % N - h;
-            const int a1 = W.M[0] * k1 + W.M[1] * k2 - W.xc[0], a2 = W.M[2] * k1 + W.M[3] * k2 - W.xc[1];
-            scale[m] = W.dec1[a1 - W.lo[0]] * W.dec2[a2 - W.lo[1]] / N;
-        }
+        const std::vector<double> scale = member_scale(N, W);
         FIO_HIP_TRY(hipMemcpy(d_rows, rows.data(), rr * sizeof(double4), hipMemcpyHostToDevice));
         FIO_HIP_TRY(hipMemcpy(d_mat, W.P.data(), W.P.size() * sizeof(double2), hipMemcpyHostToDevice));
         FIO_HIP_TRY(hipMemcpy(d_scale, scale.data(), scale.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -798,7 +809,7 @@ void release_layout(fio_plan_s *P) {
 
 // Offsets, work items, device tables, factor storage and workspace for the
 // ranks currently in P->wedges[*].q.
-static fio_status plan_layout(fio_plan_s *P) {
+fio_status plan_layout(fio_plan_s *P) {
     const int N = P->N;
     const long long NN = (long long)N * N;
     const int h = N / 2;
@@ -1248,6 +1259,8 @@ fio_status save_plan(const fio_plan_s *P, const char *path) {
     if (P->factor_mode == FIO_FACTORS_LEARNED)
         return (set_error("a plan with learned factors is kept by saving its network (fio_learned_save)"),
                 FIO_ENOTSUP);
+    if (P->factor_mode == FIO_FACTORS_TAYLOR)
+        return (set_error("plan files hold the randomized separation; Taylor factors are rebuilt"), FIO_ENOTSUP);
     FILE *f = std::fopen(path, "wb");
     if (!f)
         return (set_error(std::string("cannot open ") + path + " for writing"), FIO_EINVAL);
@@ -1497,7 +1510,7 @@ fio_status build_plan(fio_plan_s *P) {
         }
     }
     if (!use_net) {
-        st = plan_exact(P, d_xcoef);
+        st = P->opt.factor_mode == FIO_FACTORS_TAYLOR ? plan_taylor(P, d_xcoef) : plan_exact(P, d_xcoef);
         if (st != FIO_OK)
             return st;
     }

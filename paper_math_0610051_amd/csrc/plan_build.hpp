@@ -29,6 +29,12 @@ fio_status save_plan(const fio_plan_s *P, const char *path);
 fio_status load_plan(fio_plan_s *P, const char *path);
 void release_layout(fio_plan_s *P);
 std::vector<int> sample_members(int n, int k, uint64_t &state);
+std::vector<long long> sample_points(long long n, int k, uint64_t &state);
+std::vector<double> member_scale(int N, const WedgeHost &W);
+// Device layout of the plan's tables, factors and workspace from the wedge ranks.
+fio_status plan_layout(fio_plan_s *P);
+// Deterministic separated factors of Section 3.1 (FIO_FACTORS_TAYLOR).
+fio_status plan_taylor(fio_plan_s *P, const double2 *d_xcoef);
 fio_status gram_of_columns(const Phase &ph, int N, double2 *d_xcoef, double theta, const std::vector<double2> &cols,
                            DeviceScratch &scr, std::vector<zd> &G, bool fill_xcoef = true);
 

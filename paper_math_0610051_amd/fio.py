@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "FIO_OK", -1: "FIO_EINVAL", -2: "FIO_ENOMEM", -3: "FIO_EDEVIC
 PHASE_KINDS = {"linear": 0, "wave": 1, "c1c2": 2, "radial": 3, "paper_ellipse": 4, "paper_circle": 5}
 PRECISIONS = {"f32": 0, "f64": 1}
 PARTITIONS = {"equiangular": 0, "coronae": 1}
-FACTOR_MODES = {"auto": 0, "stored": 1, "regen": 2, "learned": 3}
+FACTOR_MODES = {"auto": 0, "stored": 1, "regen": 2, "learned": 3, "taylor": 4}
 
 
 class FioError(RuntimeError):

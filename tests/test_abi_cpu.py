@@ -104,7 +104,9 @@ def _plan_status(N=64, kind=2, tol=1e-4, amp_kind=0, **opts):
     (dict(kernel_width=40), fio.FIO_EINVAL),
     (dict(sigma=1.1), fio.FIO_EINVAL),
     (dict(sep_tol_frac=0.0), fio.FIO_EINVAL),
-    (dict(factor_mode=3), fio.FIO_EINVAL),
+    (dict(factor_mode=3), fio.FIO_EINVAL),        # learned without a network
+    (dict(factor_mode=5), fio.FIO_EINVAL),        # past FIO_FACTORS_TAYLOR
+    (dict(factor_mode=-1), fio.FIO_EINVAL),
 ])
 def test_invalid_plans_are_rejected_before_device_use(kw, status):
     st, h = _plan_status(**kw)
