@@ -95,7 +95,9 @@ enum { FIO_PART_EQUIANGULAR = 0, FIO_PART_CORONAE = 1 };
  * sampled columns C and Z = V S^-1, and the apply recomputes
  * gamma^x(x) = A(x, C) Z from the FP64 residual phase (Section 3.2, the
  * storage-compressed form): far less memory, more arithmetic per apply, and
- * available while the padded rank is at most 16 (FP32) or 8 (FP64);
+ * available while the padded rank is at most 16 (FP32) or 8 (FP64); FP32
+ * plans regenerate gamma^x in FP32 (phases reduced in FP64) and take the
+ * amplitude a = 1 only (FIO_ENOTSUP otherwise);
  * LEARNED takes gamma^x from a trained network; TAYLOR builds both factors by
  * the deterministic preprocessing of Section 3.1 (polar Taylor expansion of
  * the residual phase, truncated exponential series, QR and SVD compression

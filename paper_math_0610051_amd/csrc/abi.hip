@@ -158,6 +158,10 @@ fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, 
         return (set_error("unknown factor mode"), FIO_EINVAL);
     if (o.factor_mode == FIO_FACTORS_LEARNED && !o.learned)
         return (set_error("FIO_FACTORS_LEARNED needs a trained network"), FIO_EINVAL);
+    // FP32 plans regenerate gamma^x in FP32 from the phase alone
+    if (o.factor_mode == FIO_FACTORS_REGEN && o.precision == FIO_F32 && ak != FIO_AMP_ONE)
+        return (set_error("FIO_FACTORS_REGEN with an amplitude needs FIO_F64 (or use FIO_FACTORS_STORED)"),
+                FIO_ENOTSUP);
     fio_plan_s *P = new (std::nothrow) fio_plan_s();
     if (!P)
         return (set_error("host allocation failed"), FIO_ENOMEM);

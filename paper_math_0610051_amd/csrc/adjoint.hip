@@ -24,6 +24,7 @@
 // workspace hold the intermediate results, as in the forward apply.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include <rocprim/device/device_segmented_radix_sort.hpp>
 
@@ -275,7 +276,23 @@ __global__ __launch_bounds__(kThreads) void k_spread(PlanArgs<T> a, const AdjBin
                         const int k = cc - c0;
                         wc[cc] = k >= 0 && k < W ? es_weight<T>(f2 - T(k), a.two_over_w, a.beta) : T(0);
                     }
-                    if constexpr (REGEN) {  // q <= kRegenMaxRank: one round of ranks
+                    if constexpr (REGEN && sizeof(T) == 4) {  // as the interpolation regenerates it
+                        auto put = [&](auto kq) {
+                            constexpr int K = decltype(kq)::value;
+                            float ar[K], ai[K];
+                            regen_sums_f32<K>(a.phase, c, g1, g2, a.zcol + wd.zc_off, a.zmat32 + wd.zm_off, wd.zrc,
+                                              q, ar, ai);
+#pragma unroll
+                            for (int t = 0; t < K; ++t)
+                                if (t < q)
+                                    sgx[lane * qstage + t] = cmake<T>(ar[t], ai[t]);
+                        };
+                        if (q <= 8)
+                            put(std::integral_constant<int, 8>());
+                        else
+                            put(std::integral_constant<int, kRegenMaxRank>());
+                    }
+                    if constexpr (REGEN && sizeof(T) == 8) {  // q <= kRegenMaxRank: one round of ranks
                         const double2 *zc = a.zcol + wd.zc_off;
                         const double2 *zm = a.zmat + wd.zm_off;
                         double ar[kRegenMaxRank], ai[kRegenMaxRank];

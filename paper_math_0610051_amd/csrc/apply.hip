@@ -17,6 +17,7 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "apply.hpp"
 #include "interp_util.hpp"
@@ -194,6 +195,7 @@ __device__ __forceinline__ InstArgs<T> load_inst(const InstArgs<T> *inst, int i)
     a.G = as_global(a.G);
     a.zcol = as_global(a.zcol);
     a.zmat = as_global(a.zmat);
+    a.zmat32 = as_global(a.zmat32);
     I.fhat = as_global(I.fhat);
     I.u = as_global(I.u);
     return I;
@@ -409,6 +411,43 @@ __device__ __forceinline__ cplx<T> rotate_rhs(const cplx<T> &mod, const cplx<T> 
         }                                                 \
     } while (0)
 
+// gamma^x(x, t) = sum_c A(x, C_c) Z(c, t) of one point in FP64 (FP64 plans,
+// amplitude included), into the LDS rows [t / CPU][thread].
+template <typename T>
+__device__ __forceinline__ void regen_gx_f64(const PlanArgs<T> &a, const WedgeDev &wd, XCoef c, double g1, double g2,
+                                          cplx<T> *gxl, int tid) {
+    constexpr int CPU = 16 / (int)sizeof(cplx<T>);
+    const int q = wd.q;
+    const double2 *zc = a.zcol + wd.zc_off;
+    const double2 *zm = a.zmat + wd.zm_off;
+    constexpr int kC = 8;
+    for (int t0 = 0; t0 < q; t0 += kC) {
+        double ar[kC], ai[kC];
+#pragma unroll
+        for (int t = 0; t < kC; ++t)
+            ar[t] = ai[t] = 0;
+        for (int cc = 0; cc < wd.zrc; ++cc) {
+            const double2 k = zc[cc];
+            double cs2, sn2;
+            residual_entry(a.phase, c, g1, g2, k.x, k.y, cs2, sn2);
+            const double2 *zr = zm + (long long)cc * q + t0;
+#pragma unroll
+            for (int t = 0; t < kC; ++t)
+                if (t0 + t < q) {
+                    const double2 z = zr[t];
+                    ar[t] += cs2 * z.x - sn2 * z.y;
+                    ai[t] += cs2 * z.y + sn2 * z.x;
+                }
+        }
+#pragma unroll
+        for (int t = 0; t < kC; ++t)
+            if (t0 + t < q) {
+                const int tt = t0 + t;
+                gxl[((tt / CPU) * kThreads + tid) * CPU + tt % CPU] = cmake<T>((T)ar[t], (T)ai[t]);
+            }
+    }
+}
+
 template <typename T, int W, bool REGEN>
 __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__restrict__ u, long long ustride, int B,
                                             int bofs, int l0, int l1, int tile) {
@@ -448,39 +487,31 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         double g1, g2;
         phase_grad(a.phase, c, wd.e1, wd.e2, g1, g2);
         // FIO_FACTORS_REGEN: gamma^x(x, t) = sum_c A(x, C_c) Z(c, t) for this
-        // thread's point from the FP64 residual phase, into LDS after the
-        // window ([t / CPU][thread] units; each thread reads only its own)
+        // thread's point from the residual phase (reduced in FP64), into LDS
+        // after the window ([t / CPU][thread] units; each thread reads only its own)
         cplx<T> *gxl = reinterpret_cast<cplx<T> *>(smem_raw + win_bytes);
         // the staged path reads gamma^x from LDS; larger ranks take the direct path
         const bool gx_lds = REGEN || a.qmax <= kGxLdsMaxRank<T>;
-        if constexpr (REGEN) {
-            const double2 *zc = a.zcol + wd.zc_off;
-            const double2 *zm = a.zmat + wd.zm_off;
-            constexpr int kC = 8;
-            for (int t0 = 0; t0 < q; t0 += kC) {
-                double ar[kC], ai[kC];
+        if constexpr (REGEN && sizeof(T) == 8) {
+            regen_gx_f64<T>(a, wd, c, g1, g2, gxl, tid);
+        } else if constexpr (REGEN) {
+            {
+                // FP32 plans use gamma^x in FP32: the entries' phases in FP64,
+                // their exponentials and the sums over the columns in FP32
+                // (amplitude a = 1: FP32 plans do not regenerate with amplitudes)
+                auto put = [&](auto kq) {
+                    constexpr int K = decltype(kq)::value;
+                    float ar[K], ai[K];
+                    regen_sums_f32<K>(a.phase, c, g1, g2, a.zcol + wd.zc_off, a.zmat32 + wd.zm_off, wd.zrc, q, ar, ai);
 #pragma unroll
-                for (int t = 0; t < kC; ++t)
-                    ar[t] = ai[t] = 0;
-                for (int cc = 0; cc < wd.zrc; ++cc) {
-                    const double2 k = zc[cc];
-                    double cs2, sn2;
-                    residual_entry(a.phase, c, g1, g2, k.x, k.y, cs2, sn2);
-                    const double2 *zr = zm + (long long)cc * q + t0;
-#pragma unroll
-                    for (int t = 0; t < kC; ++t)
-                        if (t0 + t < q) {
-                            const double2 z = zr[t];
-                            ar[t] += cs2 * z.x - sn2 * z.y;
-                            ai[t] += cs2 * z.y + sn2 * z.x;
-                        }
-                }
-#pragma unroll
-                for (int t = 0; t < kC; ++t)
-                    if (t0 + t < q) {
-                        const int tt = t0 + t;
-                        gxl[((tt / CPU) * kThreads + tid) * CPU + tt % CPU] = cmake<T>((T)ar[t], (T)ai[t]);
-                    }
+                    for (int t = 0; t < K; ++t)
+                        if (t < q)
+                            gxl[((t / CPU) * kThreads + tid) * CPU + t % CPU] = cmake<T>(ar[t], ai[t]);
+                };
+                if (q <= 8)
+                    put(std::integral_constant<int, 8>());
+                else
+                    put(std::integral_constant<int, kRegenMaxRank>());
             }
         }
         const double y1 = x1 + g1, y2 = x2 + g2;
@@ -818,6 +849,7 @@ PlanArgs<T> make_args(const fio_plan_s *P) {
     a.G_stride = P->G_total;
     a.zcol = static_cast<const double2 *>(P->d_zcol);
     a.zmat = static_cast<const double2 *>(P->d_zmat);
+    a.zmat32 = static_cast<const float2 *>(P->d_zmat32);
     return a;
 }
 

@@ -5,6 +5,7 @@
 #pragma once
 
 #include <cfloat>
+#include <cstdint>
 
 #include "common.hpp"
 
@@ -58,6 +59,47 @@ __device__ __forceinline__ T es_weight(T z, T two_over_w, T beta) {
         return s > 0.0f ? __builtin_amdgcn_exp2f(beta * 1.44269504f * (__builtin_amdgcn_sqrtf(s) - 1.0f)) : 0.0f;
     } else {
         return es_kernel<T>(z, two_over_w, beta);
+    }
+}
+
+// A plan constant read at wave-uniform addresses through the constant
+// address space: the compiler then issues scalar loads, which batch and
+// run ahead of the vector work, instead of one vector load and wait per value.
+template <typename P>
+__device__ __forceinline__ const __attribute__((address_space(4))) P *as_constant(const P *p) {
+    return (const __attribute__((address_space(4))) P *)(uintptr_t)p;
+}
+
+// FP32 regeneration of one point's separated factor (the storage-compressed
+// form of the randomized separation): sums over the sampled columns c <
+// zrc of A(x, C_c) Z(c, t), t < K, with each entry's phase in FP64, reduced
+// by its nearest integer, and its exponential and the sums in FP32.  The K
+// values Z(c, 0 .. K-1) of a column (row stride q <= K) are read at once as
+// scalar loads; past q they belong to the next column or to the array's
+// padding, and those sums are not used.
+template <int K>
+__device__ __forceinline__ void regen_sums_f32(const Phase &ph, XCoef c, double g1, double g2, const double2 *zcol,
+                                               const float2 *zmat, int zrc, int q, float (&ar)[K], float (&ai)[K]) {
+    const auto *zc = as_constant(reinterpret_cast<const double *>(zcol));  // (k1, k2) per column
+    const auto *zm = as_constant(reinterpret_cast<const float *>(zmat));   // (re, im) per column and rank
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+        ar[t] = ai[t] = 0.0f;
+    for (int cc = 0; cc < zrc; ++cc) {
+        float cs, sn;
+        residual_entry_f32(ph, c, g1, g2, zc[2 * cc], zc[2 * cc + 1], cs, sn);
+        const auto *zr = zm + 2ll * cc * q;
+        float zre[K], zim[K];
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            zre[t] = zr[2 * t];
+            zim[t] = zr[2 * t + 1];
+        }
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            ar[t] += cs * zre[t] - sn * zim[t];
+            ai[t] += cs * zim[t] + sn * zre[t];
+        }
     }
 }
 

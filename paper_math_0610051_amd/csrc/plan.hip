@@ -675,6 +675,11 @@ static fio_status store_factors(fio_plan_s *P, const double2 *d_xcoef, bool exac
                                   hipMemcpyHostToDevice));
             FIO_HIP_TRY(hipMemcpy(static_cast<double2 *>(P->d_zmat) + D.zm_off, zp.data(), zp.size() * sizeof(double2),
                                   hipMemcpyHostToDevice));
+            std::vector<float2> zf(zp.size());
+            for (size_t i = 0; i < zp.size(); ++i)
+                zf[i] = make_float2((float)zp[i].x, (float)zp[i].y);
+            FIO_HIP_TRY(hipMemcpy(static_cast<float2 *>(P->d_zmat32) + D.zm_off, zf.data(), zf.size() * sizeof(float2),
+                                  hipMemcpyHostToDevice));
         } else if (exact_x) {
             std::vector<double2> cols(rc);
             for (int c = 0; c < rc; ++c) {
@@ -792,7 +797,7 @@ void release_layout(fio_plan_s *P) {
     void **bufs[] = {(void **)&P->d_wedges, (void **)&P->d_fftplans, (void **)&P->d_rows, (void **)&P->d_cols,
                      (void **)&P->d_map,    (void **)&P->d_omega,    &P->d_gxi,             &P->d_gx,
                      &P->d_tw,              &P->d_H,                 &P->d_G,               &P->d_zcol,
-                     &P->d_zmat,            (void **)&P->d_adj_bins, (void **)&P->d_adj_pts,
+                     &P->d_zmat,            &P->d_zmat32,            (void **)&P->d_adj_bins, (void **)&P->d_adj_pts,
                      (void **)&P->d_adj_ref};
     for (void **b : bufs) {
         if (*b)
@@ -979,6 +984,9 @@ fio_status plan_layout(fio_plan_s *P) {
     if (P->regen) {
         FIO_HIP_TRY(hipMalloc(&P->d_zcol, sizeof(double2) * std::max<long long>(1, zc_off)));
         FIO_HIP_TRY(hipMalloc(&P->d_zmat, sizeof(double2) * std::max<long long>(1, zm_off)));
+        // padded: the regeneration reads kRegenMaxRank values of a column at once
+        FIO_HIP_TRY(hipMalloc(&P->d_zmat32, sizeof(float2) * (zm_off + kRegenMaxRank)));
+        FIO_HIP_TRY(hipMemset(P->d_zmat32, 0, sizeof(float2) * (zm_off + kRegenMaxRank)));
         P->factor_bytes += (long long)sizeof(double2) * (zc_off + zm_off);
     }
     // workspace: bchunk right-hand sides

@@ -80,6 +80,7 @@ struct PlanArgs {
     long long H_stride, G_stride;  // per right-hand side
     const double2 *zcol;           // regenerated factors (FIO_FACTORS_REGEN)
     const double2 *zmat;
+    const float2 *zmat32;          // Z in FP32 (FP32 plans)
 };
 
 struct WedgeHost {
@@ -112,7 +113,7 @@ struct fio_plan_s {
     double plan_ms = 0;
     double learned_sep_err = 0, learned_ms = 0;  // the learned attempt, if any
     bool regen = false;                          // gamma^x recomputed in the apply
-    void *d_zcol = nullptr, *d_zmat = nullptr;
+    void *d_zcol = nullptr, *d_zmat = nullptr, *d_zmat32 = nullptr;
     std::vector<fio::WedgeHost> wedges;
     std::vector<int> wedge_of;   // N*N, centred
     std::vector<fio::WedgeDev> wdev;

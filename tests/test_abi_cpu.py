@@ -106,6 +106,7 @@ def _plan_status(N=64, kind=2, tol=1e-4, amp_kind=0, **opts):
     (dict(sep_tol_frac=0.0), fio.FIO_EINVAL),
     (dict(factor_mode=3), fio.FIO_EINVAL),        # learned without a network
     (dict(factor_mode=5), fio.FIO_EINVAL),        # past FIO_FACTORS_TAYLOR
+    (dict(factor_mode=2, amp_kind=1), fio.FIO_ENOTSUP),  # FP32 regeneration takes a = 1 only
     (dict(factor_mode=-1), fio.FIO_EINVAL),
 ])
 def test_invalid_plans_are_rejected_before_device_use(kw, status):
