@@ -92,8 +92,10 @@ enum { FIO_F32 = 0, FIO_F64 = 1 };
 enum { FIO_PART_EQUIANGULAR = 0, FIO_PART_CORONAE = 1 };
 /* Factor modes.  STORED keeps gamma^x for every grid point (N^2 q complex per
  * wedge); REGEN keeps only the compressed factors of eq. (probnewfac), the
- * sampled columns C and Z = V S^-1, and the apply recomputes
- * gamma^x(x) = A(x, C) Z from the FP64 residual phase (Section 3.2, the
+ * sampled columns C and Z = V S^-1 (reduced to about rank-many columns C' by
+ * an interpolative decomposition, A(:, C) ~ A(:, C') W, Z' = W Z, where the
+ * s x s estimate accepts it), and the apply recomputes
+ * gamma^x(x) = A(x, C') Z' from the residual phase (Section 3.2, the
  * storage-compressed form): far less memory, more arithmetic per apply, and
  * available while the padded rank is at most 16 (FP32) or 8 (FP64); FP32
  * plans regenerate gamma^x in FP32 (phases reduced in FP64) and take the

@@ -195,4 +195,76 @@ void pinv_tall(int m, int k, const std::vector<zd> &U, std::vector<zd> &P, doubl
         }
 }
 
+// Column interpolative decomposition by Householder QR with column pivoting
+// (Golub and Van Loan, Section 5.4.1; Cheng, Gimbutas, Martinsson and
+// Rokhlin, "On the compression of low rank matrices", 2005).  Step j swaps
+// the remaining column of largest norm into place and stops once that norm
+// is at most tol times the first pivot's; with k steps taken, A P = Q [R11
+// R12] on the leading k rows gives A(:, P(k..n)) ~ A(:, P(0..k)) T,
+// T = R11^-1 R12.
+int column_id(int m, int n, std::vector<zd> A, double tol, std::vector<int> &perm, std::vector<zd> &T) {
+    auto at = [&](int i, int j) -> zd & { return A[(size_t)i * n + j]; };
+    perm.resize(n);
+    std::iota(perm.begin(), perm.end(), 0);
+    const int kmax = std::min(m, n);
+    double first = 0;
+    int k = 0;
+    std::vector<zd> v(m);
+    for (; k < kmax; ++k) {
+        // column of largest norm in rows k..m-1
+        int best = k;
+        double bn = -1;
+        for (int j = k; j < n; ++j) {
+            double s = 0;
+            for (int i = k; i < m; ++i)
+                s += std::norm(at(i, j));
+            if (s > bn) {
+                bn = s;
+                best = j;
+            }
+        }
+        bn = std::sqrt(bn);
+        if (k == 0)
+            first = bn;
+        if (bn <= tol * first || bn == 0)
+            break;
+        if (best != k) {
+            for (int i = 0; i < m; ++i)
+                std::swap(at(i, k), at(i, best));
+            std::swap(perm[k], perm[best]);
+        }
+        // reflector mapping column k (rows k..) onto alpha e_k
+        const zd x0 = at(k, k);
+        const double ax0 = std::abs(x0);
+        const zd alpha = -(ax0 > 0 ? x0 / ax0 : zd(1, 0)) * bn;
+        double vn = 0;
+        for (int i = k; i < m; ++i) {
+            v[i] = at(i, k) - (i == k ? alpha : zd(0, 0));
+            vn += std::norm(v[i]);
+        }
+        vn = std::sqrt(vn);
+        if (vn > 0) {
+            for (int i = k; i < m; ++i)
+                v[i] /= vn;
+            for (int j = k; j < n; ++j) {
+                zd d(0, 0);
+                for (int i = k; i < m; ++i)
+                    d += std::conj(v[i]) * at(i, j);
+                for (int i = k; i < m; ++i)
+                    at(i, j) -= 2.0 * v[i] * d;
+            }
+        }
+    }
+    // T = R11^-1 R12 by back substitution, k x (n - k)
+    T.assign((size_t)k * (n - k), zd(0, 0));
+    for (int c = 0; c < n - k; ++c)
+        for (int i = k - 1; i >= 0; --i) {
+            zd s = at(i, k + c);
+            for (int j = i + 1; j < k; ++j)
+                s -= at(i, j) * T[(size_t)j * (n - k) + c];
+            T[(size_t)i * (n - k) + c] = s / at(i, i);
+        }
+    return k;
+}
+
 }  // namespace fio

@@ -21,4 +21,10 @@ int eigh(int n, std::vector<zd> &A, std::vector<double> &w, std::vector<zd> &V);
 // rcond * s_max discarded.  P is k x m (row-major).
 void pinv_tall(int m, int k, const std::vector<zd> &U, std::vector<zd> &P, double rcond);
 
+// Column interpolative decomposition of A (m x n, row-major): returns k and
+// a column order perm such that A(:, perm[k..n)) ~ A(:, perm[0..k)) T (T is
+// k x (n - k), row-major); pivoting stops at a remaining column norm of
+// tol times the first pivot's.
+int column_id(int m, int n, std::vector<zd> A, double tol, std::vector<int> &perm, std::vector<zd> &T);
+
 }  // namespace fio

@@ -1001,6 +1001,72 @@ fio_status plan_layout(fio_plan_s *P) {
     return FIO_OK;
 }
 
+// FIO_FACTORS_REGEN regenerates gamma^x(x) = A(x, C) Z with a sum over all r
+// sampled columns.  A column interpolative decomposition of A(R, C) on the
+// sampled rows keeps k of them, A(:, C) ~ A(:, C') [I T] P^T, so that
+// gamma^x = A(x, C') Z' with Z' = [I T] P^T Z: k (near the rank) columns per
+// point instead of r.  Errors in A(:, C) reach the operator through Z, which
+// scales the weakest directions up, so the decomposition is cut far below
+// the separation threshold; the s x s estimate then decides whether the
+// wedge keeps it.
+static void regen_column_id(fio_plan_s *P, int l) {
+    WedgeHost &W = P->wedges[l];
+    const int N = P->N, h = N / 2, rc = (int)W.C.size(), rr = (int)W.R.size(), q = W.q;
+    if (q == 0 || rc <= q + 2)
+        return;
+    const double e1 = std::cos(W.theta), e2 = std::sin(W.theta);
+    auto col = [&](int c, double &k1, double &k2) {
+        const int om = W.members[W.C[c]];
+        k1 = om / N - h;
+        k2 = om % N - h;
+    };
+    std::vector<zd> M((size_t)rr * rc);
+    for (int i = 0; i < rr; ++i)
+        for (int c = 0; c < rc; ++c) {
+            double k1, k2;
+            col(c, k1, k2);
+            M[(size_t)i * rc + c] = host_residual(P->phase, N, W.R[i], e1, e2, k1, k2);
+        }
+    std::vector<int> perm;
+    std::vector<zd> T;
+    const double thr = P->tol * P->opt.sep_tol_frac;
+    const int k = column_id(rr, rc, M, 1e-3 * thr, perm, T);
+    if (k <= 0 || k >= rc)
+        return;
+    std::vector<zd> Z2((size_t)k * q);
+    for (int j = 0; j < k; ++j)
+        for (int t = 0; t < q; ++t) {
+            zd s = W.Z[(size_t)perm[j] * q + t];
+            for (int i = k; i < rc; ++i)
+                s += T[(size_t)j * (rc - k) + (i - k)] * W.Z[(size_t)perm[i] * q + t];
+            Z2[(size_t)j * q + t] = s;
+        }
+    // s x s estimate with the reduced columns
+    uint64_t state = splitmix64(P->opt.seed ^ (0x1DC0ull * (uint64_t)(l + 1)));
+    const long long NN = (long long)N * N;
+    const int sv = std::max(8, P->opt.verify_samples), nmem = (int)W.members.size();
+    const std::vector<long long> Gam = sample_distinct<long long>(NN, (int)std::min<long long>(sv, NN), state);
+    const std::vector<int> Del = sample_distinct<int>(nmem, std::min(sv, nmem), state);
+    std::vector<zd> UG(Gam.size() * (size_t)q, zd(0, 0));
+    for (size_t i = 0; i < Gam.size(); ++i)
+        for (int j = 0; j < k; ++j) {
+            double k1, k2;
+            col(perm[j], k1, k2);
+            const zd a = host_residual(P->phase, N, Gam[i], e1, e2, k1, k2);
+            for (int t = 0; t < q; ++t)
+                UG[i * q + t] += a * Z2[(size_t)j * q + t];
+        }
+    const double err = separation_estimate(P, W, Gam, Del, UG);
+    if (err > std::max(0.5 * P->tol, 1.2 * W.sep_err))
+        return;
+    std::vector<int> C2(k);
+    for (int j = 0; j < k; ++j)
+        C2[j] = W.C[perm[j]];
+    W.C = C2;
+    W.Z = Z2;
+    W.sep_err = std::max(W.sep_err, err);
+}
+
 // Exact factors: randomized separation of every wedge, then storage.
 static fio_status plan_exact(fio_plan_s *P, const double2 *d_xcoef) {
     {
@@ -1020,6 +1086,9 @@ static fio_status plan_exact(fio_plan_s *P, const double2 *d_xcoef) {
         }
     }
     P->regen = P->opt.factor_mode == FIO_FACTORS_REGEN;
+    if (P->regen)
+        for (int l = 0; l < P->L; ++l)
+            regen_column_id(P, l);
     if (P->regen) {
         int qmax = 0;
         for (const WedgeHost &W : P->wedges)

@@ -305,9 +305,11 @@ def test_other_oversampling_factors_full_grid(sigma):
 @pytest.mark.parametrize("precision", ["f32", "f64"])
 def test_regenerated_factors_match_stored_ones(precision):
     """FIO_FACTORS_REGEN keeps only the compressed factors (sampled columns and
-    Z = V S^-1) and recomputes gamma^x in the apply.  With the same seed the
-    separation is the same, so the apply must agree with the stored-factor
-    plan to rounding, meet the tolerance, and hold far fewer factor bytes."""
+    Z = V S^-1), reduced to the columns an interpolative decomposition keeps
+    (far below the separation threshold), and recomputes gamma^x in the
+    apply.  With the same seed the separation is the same, so the apply must
+    agree with the stored-factor plan far inside the tolerance, meet the
+    tolerance, and hold far fewer factor bytes."""
     N, tol = 128, 1e-4
     rng = fi.rng_for(1, 5)
     fh = fi.fhat_from_f(fi.complex_gaussian(N, rng, B=3))
@@ -322,18 +324,21 @@ def test_regenerated_factors_match_stored_ones(precision):
     fs, fr = ps.info()["factor_bytes"], pr.info()["factor_bytes"]
     print("  %s: regen vs stored %.2e, regen vs direct %.2e, factor bytes %d -> %d"
           % (precision, diff, err, fs, fr))
-    assert diff < (2e-6 if precision == "f32" else 1e-12)
+    assert diff < 0.02 * tol
     assert err <= tol
     assert fr * 4 < fs
-    # the exported spatial factors agree: host FP64 regeneration against the
-    # stored ones (device FP64, then the plan precision); host and device
-    # exponentials differ in the last bits, which the sum with Z ~ 1/s_q
-    # amplifies, hence 1e-10 in FP64
+    # the exported spatial factors agree: host FP64 regeneration from the
+    # kept columns against the stored ones from all sampled columns; their
+    # difference is the decomposition's, which the sum with Z ~ 1/s_q scales
+    # up in the weakest factors (whose gamma^xi are small: the applies above
+    # differ by 2e-7)
     xs = np.arange(0, N * N, 97)
     for ell in (0, pr.L // 3):
         gr, _ = pr.wedge_factors(ell, xs)
         gs, _ = ps.wedge_factors(ell, xs)
-        assert np.linalg.norm(gr - gs) <= (1e-6 if precision == "f32" else 1e-10) * np.linalg.norm(gs)
+        rel = np.linalg.norm(gr - gs) / np.linalg.norm(gs)
+        print("  wedge %d: spatial factors differ by %.2e" % (ell, rel))
+        assert rel <= tol
 
 
 def test_fp64_long_columns_in_rank_chunks():
