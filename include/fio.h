@@ -287,6 +287,14 @@ const char *fio_last_error(void);
  * eigenvalues in descending order, V: n x n eigenvectors as columns
  * (row-major). */
 fio_status fio_host_eigh(int n, const double *A, double *w, double *V);
+/* Column interpolative decomposition of an m x n complex double matrix A
+ * (row-major, interleaved) by Householder QR with column pivoting, stopped
+ * at a remaining column norm of tol times the first pivot's (the reduction
+ * of FIO_FACTORS_REGEN's columns).  *k receives the number of kept columns;
+ * perm (n) the column order, kept columns first; T (k x (n - k) complex,
+ * row-major; room for n x n) with A(:, perm[k..n)) ~ A(:, perm[0..k)) T.
+ * FIO_EINVAL on bad sizes or null pointers. */
+fio_status fio_host_column_id(int m, int n, const double *A, double tol, int *k, int *perm, double *T);
 
 /* Relative l2 error (the Section 4 estimator) of a computed u = L fhat at
  * nsamples grid points drawn from `seed`, against an FP64 direct summation of

@@ -583,4 +583,22 @@ fio_status fio_host_eigh(int n, const double *A, double *w, double *V) {
     return FIO_OK;
 }
 
+fio_status fio_host_column_id(int m, int n, const double *A, double tol, int *k, int *perm, double *T) {
+    set_error("");
+    if (m < 1 || n < 1 || m > 4096 || n > 4096 || !A || !k || !perm || !T || !(tol >= 0))
+        return (set_error("bad argument"), FIO_EINVAL);
+    std::vector<zd> M((size_t)m * n), Tm;
+    for (size_t i = 0; i < M.size(); ++i)
+        M[i] = zd(A[2 * i], A[2 * i + 1]);
+    std::vector<int> pv;
+    *k = column_id(m, n, M, tol, pv, Tm);
+    for (int j = 0; j < n; ++j)
+        perm[j] = pv[j];
+    for (size_t i = 0; i < Tm.size(); ++i) {
+        T[2 * i] = Tm[i].real();
+        T[2 * i + 1] = Tm[i].imag();
+    }
+    return FIO_OK;
+}
+
 }  // extern "C"

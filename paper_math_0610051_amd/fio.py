@@ -121,6 +121,7 @@ def load_library():
                                  c_int, P, c_int, P, POINTER(fio_tune_result_t)]),
         "fio_last_error": (c_char_p, []),
         "fio_host_eigh": (c_int, [c_int, P, P, P]),
+        "fio_host_column_id": (c_int, [c_int, c_int, P, c_double, POINTER(c_int), P, P]),
         "fio_version": (c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -147,13 +148,27 @@ def make_phase(kind, params=()):
 
 
 def host_eigh(A: np.ndarray):
-    """The library's host Jacobi eigen-solver (for CPU tests of the plan's linear algebra)."""
+    """The library's host Hermitian eigen-solver (for CPU tests of the plan's linear algebra)."""
     A = np.ascontiguousarray(A, dtype=np.complex128)
     n = A.shape[0]
     w = np.empty(n)
     V = np.empty((n, n), dtype=np.complex128)
     _check(load_library().fio_host_eigh(n, A.ctypes.data, w.ctypes.data, V.ctypes.data))
     return w, V
+
+
+def host_column_id(A: np.ndarray, tol: float):
+    """The library's host column interpolative decomposition: (k, perm, T) with
+    A[:, perm[k:]] ~ A[:, perm[:k]] @ T (for CPU tests)."""
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    m, n = A.shape
+    k = c_int(0)
+    perm = np.empty(n, dtype=np.int32)
+    T = np.zeros(n * n, dtype=np.complex128)
+    _check(load_library().fio_host_column_id(m, n, A.ctypes.data, float(tol), ctypes.byref(k), perm.ctypes.data,
+                                             T.ctypes.data))
+    k = k.value
+    return k, perm, T[:k * (n - k)].reshape(k, n - k)
 
 
 def default_options() -> fio_options:

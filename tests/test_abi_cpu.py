@@ -74,6 +74,27 @@ def test_host_eigh_on_gram_of_unimodular_columns():
     np.testing.assert_allclose(w[big], (s ** 2)[big], rtol=1e-6, atol=1e-14 * s[0] ** 2)
 
 
+def test_host_column_id_reproduces_a_low_rank_matrix():
+    """An exactly rank-6 32 x 32 matrix: the decomposition keeps 6 columns,
+    the kept columns are independent, and A[:, rest] = A[:, kept] T to
+    rounding; a full-rank matrix keeps every column."""
+    rng = np.random.default_rng(9)
+    m, n, r = 32, 32, 6
+    A = (rng.standard_normal((m, r)) + 1j * rng.standard_normal((m, r))) @ \
+        (rng.standard_normal((r, n)) + 1j * rng.standard_normal((r, n)))
+    k, perm, T = fio.host_column_id(A, 1e-10)
+    assert k == r
+    assert sorted(perm) == list(range(n))
+    kept, rest = A[:, perm[:k]], A[:, perm[k:]]
+    assert np.linalg.matrix_rank(kept) == r
+    assert np.linalg.norm(rest - kept @ T) < 1e-11 * np.linalg.norm(A)
+    B = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    kb, _, _ = fio.host_column_id(B, 1e-10)
+    assert kb == n
+    # the first pivot is the column of largest norm
+    assert np.argmax(np.linalg.norm(B, axis=0)) == fio.host_column_id(B, 1e-10)[1][0]
+
+
 def _plan_status(N=64, kind=2, tol=1e-4, amp_kind=0, **opts):
     lib = fio.load_library()
     ph = fio.make_phase(kind, (1.0,))
