@@ -150,27 +150,42 @@ __global__ void k_reduce_splits(const float *__restrict__ P, int splits, int MN,
     if (i >= MN)
         return;
     float s = 0;
+#pragma unroll 8
     for (int k = 0; k < splits; ++k)
         s += P[(long long)k * MN + i];
     dst[i] = s;
 }
 
-// column sums of an n x N fp32 matrix (bias gradients), one block per column
-__global__ void k_colsum(const float *__restrict__ X, int n, int N, float *__restrict__ dst) {
+// Column sums of an n x N fp32 matrix (bias gradients), first stage: block b
+// sums rows [b rows_per_block, (b + 1) rows_per_block) of every column into
+// partial[b][c].  N divides the block size: thread t takes column t % N and
+// every (256 / N)-th row, so each row is read as one contiguous run.
+constexpr int kColsumBlocks = 128;
+static_assert(256 % kNetHidden == 0 && 256 % kNetOut == 0, "layer widths must divide the colsum block");
+__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ X, int n, int N, int rows_per_block,
+                                                     float *__restrict__ partial) {
     __shared__ float red[256];
-    const int c = blockIdx.x;
-    float s = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-        s += X[(long long)i * N + c];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o)
-            red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
+    const int t = threadIdx.x, c = t % N, lanes = 256 / N, rl = t / N;
+    const int r0 = blockIdx.x * rows_per_block, r1 = min(n, r0 + rows_per_block);
+    // four independent sums keep four rows' loads in flight
+    float s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    int r = r0 + rl;
+    for (; r + 3 * lanes < r1; r += 4 * lanes) {
+        s0 += X[(long long)r * N + c];
+        s1 += X[(long long)(r + lanes) * N + c];
+        s2 += X[(long long)(r + 2 * lanes) * N + c];
+        s3 += X[(long long)(r + 3 * lanes) * N + c];
     }
-    if (threadIdx.x == 0)
-        dst[c] = red[0];
+    for (; r < r1; r += lanes)
+        s0 += X[(long long)r * N + c];
+    float s = (s0 + s1) + (s2 + s3);
+    red[t] = s;
+    __syncthreads();
+    if (rl == 0) {
+        for (int k = 1; k < lanes; ++k)
+            s += red[k * N + c];
+        partial[(long long)blockIdx.x * N + c] = s;
+    }
 }
 
 // dY = 2 (Y - T) / n; per-block partial sums of (Y - T)^2
@@ -333,7 +348,7 @@ LearnedModel::~LearnedModel() {
 
 struct StepBuffers {
     unsigned short *X, *A[3], *dYb, *dZb[2];
-    float *T, *Z[3], *Y, *dYf, *dZf[2], *P, *part;
+    float *T, *Z[3], *Y, *dYf, *dZf[2], *P, *part, *CP;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -357,6 +372,7 @@ static hipError_t ensure_scratch(LearnedModel *M, int n) {
     bytes += 2 * align256(4 * h);                                    // dZf ping-pong
     bytes += align256(4 * (size_t)kSplitMax * kNetHidden * kNetHidden);  // split-K partials
     bytes += align256(4 * 4096);                                     // loss partials
+    bytes += align256(4 * (size_t)kColsumBlocks * kNetHidden);        // bias-gradient partials
     hipError_t e = hipMalloc(&M->scratch, bytes);
     if (e != hipSuccess)
         return e;
@@ -389,6 +405,7 @@ static StepBuffers carve(LearnedModel *M, int n) {
         b.dZf[i] = (float *)take(4 * h);
     b.P = (float *)take(4 * (size_t)kSplitMax * kNetHidden * kNetHidden);
     b.part = (float *)take(4 * 4096);
+    b.CP = (float *)take(4 * (size_t)kColsumBlocks * kNetHidden);
     return b;
 }
 
@@ -438,7 +455,10 @@ static hipError_t backward(LearnedModel *M, const StepBuffers &b, int n, double 
         const int kchunk = ((n / splits + 15) / 16) * 16;
         const int nsplit = (n + kchunk - 1) / kchunk;
         k_reduce_splits<<<(din * dout + 255) / 256, 256, 0, s>>>(b.P, nsplit, din * dout, M->d_g + M->offW[l]);
-        k_colsum<<<dout, 256, 0, s>>>(dZf, n, dout, M->d_g + M->offb[l]);
+        // db: column sums of dZ in two stages (dout divides the block size)
+        const int rpb = (n + kColsumBlocks - 1) / kColsumBlocks;
+        k_colsum_part<<<kColsumBlocks, 256, 0, s>>>(dZf, n, dout, rpb, b.CP);
+        k_reduce_splits<<<(dout + 255) / 256, 256, 0, s>>>(b.CP, kColsumBlocks, dout, M->d_g + M->offb[l]);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (l > 0) {
