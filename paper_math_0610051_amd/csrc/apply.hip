@@ -279,13 +279,13 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
 }
 
 template <typename T>
-__global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(kFftWavesPerEU))) void k_cols(
+__global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(kColWavesPerEU))) void k_cols(
     PlanArgs<T> a, const ColItem *__restrict__ items) {
     cols_body<T>(a, items[blockIdx.x], blockIdx.y);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(kFftWavesPerEU))) void k_cols_multi(
+__global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(kColWavesPerEU))) void k_cols_multi(
     const InstArgs<T> *__restrict__ inst, const MultiColItem *__restrict__ items) {
     const MultiColItem &m = items[blockIdx.x];
     const InstArgs<T> I = load_inst(inst, m.inst);

@@ -16,7 +16,8 @@ constexpr int kInterpWindowMax = 36864;  // LDS window buffers (rank planes of s
 constexpr int kInterpWindowMin = 16384;
 constexpr int kMaxLdsBytes = 131072;  // largest dynamic LDS request of any apply kernel
 constexpr int kFftThreads = 512;     // workgroup size of the two FFT stages
-constexpr int kFftWavesPerEU = 4;    // register budget: two FFT workgroups per CU overlap load, transform and store
+constexpr int kFftWavesPerEU = 4;    // register budget of the row stage: two workgroups per CU overlap load, transform and store
+constexpr int kColWavesPerEU = 6;    // at least three column-stage workgroups per CU
 constexpr int kRowLdsBytes = 32768;   // in-place FFT buffer of a row-stage workgroup
 constexpr int kColLdsBytes = 32768;   // in-place FFT buffer of a column-stage workgroup
 constexpr int kColThreads = 512;      // workgroup size of the column stage

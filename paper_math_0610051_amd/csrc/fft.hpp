@@ -184,35 +184,46 @@ __host__ __device__ inline void dft_small<double, 5>(cplx<double> *v) { dft5(v);
 // In-place Stockham pass of radix R (decimation in time) on one LDS buffer.
 // Butterfly w = j * nb + b reads buf[(j + r m) nb + b], r < R, m = n / R,
 // twiddles input r by W^(r k n / (Ns R)) with k = j mod Ns, W = exp(2 pi i / n),
-// and writes output s to buf[((j / Ns) Ns R + k + s Ns) nb + b].  Every worker
-// first transforms its butterflies into registers, the workgroup
-// synchronises, the results are written back, and it synchronises again.
-// KB bounds the butterflies per worker: (n / R) * nb <= KB * nthreads.
-// twl: the n twiddles W^i, i < n, in LDS.
+// and writes output s to buf[((j / Ns) Ns R + k + s Ns) nb + b].  KB bounds
+// the butterflies per worker: (n / R) * nb <= KB * nthreads.  twl: the n
+// twiddles W^i, i < n, in LDS (twl[0] = 1, and a product with 1 is exact, so
+// k = 0 needs no branch).  A worker issues the loads of all its butterflies,
+// elements and twiddles, before the first product, so that the LDS latencies
+// overlap; workers past the end read butterfly 0 and store nothing.  The
+// workgroup synchronises, the results are written back, and it synchronises
+// again.
 template <typename T, int R, int KB>
 __device__ __forceinline__ void stockham_pass_inplace(cplx<T> *buf, int n, int nb, const FastDiv &fnb, int Ns,
                                                       const FastDiv &fns, int tfac, const cplx<T> *twl, int tid,
                                                       int nthreads) {
     const int m = n / R;
     const int total = m * nb;
-    cplx<T> v[KB][R];
+    cplx<T> v[KB][R], tw[KB][R];
     int dst[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-        const int w = tid + k * nthreads;
-        dst[k] = -1;
-        if (w < total) {
-            const int j = fnb.div(w), b = w - j * nb;
-            const int jq = fns.div(j), kk = j - jq * Ns;
-            const int tstep = tfac * kk;
+        int w0 = tid + k * nthreads;
+        // opaque to the compiler: the butterfly addresses are recomputed in
+        // every pass instead of being held in registers across all passes
+        asm volatile("" : "+v"(w0));
+        const int w = w0 < total ? w0 : 0;
+        const int j = fnb.div(w), b = w - j * nb;
+        const int jq = fns.div(j), kk = j - jq * Ns;
+        const int tstep = tfac * kk;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const cplx<T> x = buf[(j + r * m) * nb + b];
-                v[k][r] = (r == 0 || kk == 0) ? x : cmul(x, twl[r * tstep]);
-            }
-            dft_small<T, R>(v[k]);
-            dst[k] = (jq * Ns * R + kk) * nb + b;
-        }
+        for (int r = 0; r < R; ++r)
+            v[k][r] = buf[(j + r * m) * nb + b];
+#pragma unroll
+        for (int r = 1; r < R; ++r)
+            tw[k][r] = twl[r * tstep];
+        dst[k] = w0 < total ? (jq * Ns * R + kk) * nb + b : -1;
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+#pragma unroll
+        for (int r = 1; r < R; ++r)
+            v[k][r] = cmul(v[k][r], tw[k][r]);
+        dft_small<T, R>(v[k]);
     }
     __syncthreads();
 #pragma unroll
