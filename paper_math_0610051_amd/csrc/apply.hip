@@ -48,6 +48,30 @@ __device__ __forceinline__ void store_slot(cplx<T> *buf, int code, int stride, b
         buf[pos + stride] = (code & 1) ? cmake<T>(-v.re, -v.im) : v;
 }
 
+// 16-byte unit of H, G and the staged window: two complex floats or one
+// complex double.
+template <typename T>
+struct Unit16;
+template <>
+struct Unit16<float> {
+    using type = float4;
+};
+template <>
+struct Unit16<double> {
+    using type = double2;
+};
+
+template <typename U>
+__device__ __forceinline__ U neg_unit(U v);
+template <>
+__device__ __forceinline__ float4 neg_unit(float4 v) {
+    return make_float4(-v.x, -v.y, -v.z, -v.w);
+}
+template <>
+__device__ __forceinline__ double2 neg_unit(double2 v) {
+    return make_double2(-v.x, -v.y);
+}
+
 // ---------------------------------------------------------------------------
 // Stage 1: window x factor -> box rows, FFT along axis 2 (length n2, the short
 // side of the box).  One workgroup per (wedge, nr adjacent box rows, rank
@@ -60,72 +84,90 @@ template <typename T>
 __device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it, const cplx<T> *__restrict__ fhat,
                                           long long fstride, int B) {
     constexpr int E = kRowLdsBytes / (int)sizeof(cplx<T>) / kFftThreads;
+    using U = typename Unit16<T>::type;
+    constexpr int CPU = 16 / (int)sizeof(cplx<T>);
     extern __shared__ unsigned char smem_raw[];
     cplx<T> *buf = reinterpret_cast<cplx<T> *>(smem_raw);
+    U *bu = reinterpret_cast<U *>(smem_raw);
     const WedgeDev &W = a.wedges[it.l];
     const int n = W.n2, nr = it.nr, tn = it.tn, nbt = nr * tn, q = W.q, B1 = W.B1, B2 = W.B2, lo2 = W.lo2;
+    const int k1 = it.k1, t0 = it.t0;
+    const long long H_off = W.H_off;
     const int tid = threadIdx.x, nt = blockDim.x;
     const FftPlan *pl = a.fftplans + W.fft2;
     cplx<T> *twl = buf + n * nbt;  // the n twiddles follow the transform buffer
     for (int i = tid; i < n; i += nt)
         twl[i] = a.tw[W.tw2 + i];
-    const FastDiv &ftn = it.ftn, &fb2 = W.fB2, &fnbt = it.fnbt;
+    // copies, not references: the stores to H could alias the wedge and item
+    // records as far as the compiler knows
+    const FastDiv ftn = it.ftn, fb2 = W.fB2, fnbt = it.fnbt, fnr = it.fnr, fnpl = it.fnpl;
     // the box fills at most half the row: the first radix-2 pass is folded into the scatter
     const bool pruned = pl->radix[0] == 2 && n >= 2 * B2;
-    const int *map = a.map + W.map_off + (long long)it.k1 * B2;
+    const int *map = a.map + W.map_off + (long long)k1 * B2;
     const int *omega = a.omega + W.mem_off;
-    const cplx<T> *gxi = a.gxi + W.gxi_off + it.t0;
+    const cplx<T> *gxi = a.gxi + W.gxi_off + t0;
     // This thread's box cells (row r, box column k2, rank t; rank fastest):
     // buffer position, input index and frequency factor do not depend on
-    // the right-hand side, so they are looked up once for the whole batch.
-    // (cells beyond KR * nt, possible only for oversampling below 2, are
-    // looked up per right-hand side)
+    // the right-hand side, so they are looked up once for the whole batch:
+    // the box map of every cell first, then the input indices and factors,
+    // two rounds of dependent loads.  (Cells beyond KR * nt, possible only
+    // for oversampling below 2, are looked up per right-hand side.)
     constexpr int KR = (E + 1) / 2;
+    const int ncell = nr * B2 * tn;
     int dst[KR], fidx[KR];
     cplx<T> g[KR];
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
-        const int i = tid + k * nt;
-        dst[k] = -1;
-        fidx[k] = 0;
-        g[k] = cmake<T>(0, 0);
-        if (i < nr * B2 * tn) {
-            const int rk = ftn.div(i), t = i - rk * tn;
-            const int r = fb2.div(rk), k2 = rk - r * B2;
-            const int m = map[r * B2 + k2];
-            if (m >= 0) {
-                int j2 = lo2 + k2;
-                if (j2 < 0)
-                    j2 += n;
-                dst[k] = slot_code(pruned, j2, n, nbt, r * tn + t);
-                fidx[k] = omega[m];
-                g[k] = gxi[(long long)m * q + t];
-            }
-        }
+        const int i0 = tid + k * nt, i = i0 < ncell ? i0 : 0;
+        const int rk = ftn.div(i), t = i - rk * tn;
+        const int r = fb2.div(rk), k2 = rk - r * B2;
+        const int m = map[r * B2 + k2];
+        fidx[k] = i0 < ncell ? m : -1;  // the box map entry, for now
+        int j2 = lo2 + k2;
+        if (j2 < 0)
+            j2 += n;
+        dst[k] = slot_code(pruned, j2, n, nbt, r * tn + t);
+    }
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int i0 = tid + k * nt, i = i0 < ncell ? i0 : 0;
+        const int t = i - ftn.div(i) * tn;
+        const int m = fidx[k] >= 0 ? fidx[k] : 0;
+        if (fidx[k] < 0)
+            dst[k] = -1;
+        fidx[k] = omega[m];
+        g[k] = gxi[(long long)m * q + t];
     }
     // this thread's inputs of the next right-hand side, fetched during the
-    // current one's transform
+    // current one's transform (FP32; FP64 has no registers to spare for them)
+    constexpr bool kPrefetch = sizeof(T) == 4;
     cplx<T> fv[KR];
 #pragma unroll
     for (int k = 0; k < KR; ++k)
-        if (dst[k] >= 0)
-            fv[k] = fhat[fidx[k]];
+        fv[k] = fhat[dst[k] >= 0 ? fidx[k] : 0];
+    const bool whole = tn % CPU == 0 && t0 % CPU == 0;
+    const int qu = q / CPU;
     for (int b = 0; b < B; ++b) {
-        for (int i = tid; i < n * nbt; i += nt)
-            buf[i] = cmake<T>(0, 0);
+        // n is even, so the buffer is a whole number of 16-byte units
+        for (int i = tid; i < n * nbt / CPU; i += nt)
+            bu[i] = U{};
         __syncthreads();
         const cplx<T> *f = fhat + b * fstride;
+        if (!kPrefetch && b > 0) {
+#pragma unroll
+            for (int k = 0; k < KR; ++k)
+                fv[k] = f[dst[k] >= 0 ? fidx[k] : 0];
+        }
 #pragma unroll
         for (int k = 0; k < KR; ++k)
             if (dst[k] >= 0)
                 store_slot(buf, dst[k], nbt, pruned, cmul(fv[k], g[k]));
-        if (b + 1 < B) {
+        if (kPrefetch && b + 1 < B) {
 #pragma unroll
             for (int k = 0; k < KR; ++k)
-                if (dst[k] >= 0)
-                    fv[k] = f[fstride + fidx[k]];
+                fv[k] = f[fstride + (dst[k] >= 0 ? fidx[k] : 0)];
         }
-        for (int i = tid + KR * nt; i < nr * B2 * tn; i += nt) {
+        for (int i = tid + KR * nt; i < ncell; i += nt) {
             const int rk = ftn.div(i), t = i - rk * tn;
             const int r = fb2.div(rk), k2 = rk - r * B2;
             const int m = map[r * B2 + k2];
@@ -140,23 +182,20 @@ __device__ __forceinline__ void rows_body(const PlanArgs<T> &a, const RowItem it
         __syncthreads();
         fft_inplace<T, E>(buf, pl, n, nbt, fnbt, twl, tid, nt, pruned ? 1 : 0);
         // buf[j2 * nbt + r * tn + t] -> H[((j2 * qu + (t0 + t) / CPU) * B1 + k1 + r) * CPU + (t0 + t) % CPU]
-        constexpr int CPU = 16 / (int)sizeof(cplx<T>);
-        const int qu = q / CPU;
-        cplx<T> *H = a.H + b * a.H_stride + W.H_off;
-        if (tn % CPU == 0 && it.t0 % CPU == 0) {
-            // whole planes: flat i = ((j2 * npl + pl) * nr + r) * CPU + c follows H
+        cplx<T> *H = a.H + b * a.H_stride + H_off;
+        if (whole) {
+            // whole planes: 16-byte unit u = (j2 * npl + pl) * nr + r follows H
+            U *Hu = reinterpret_cast<U *>(H);
             const int npl = tn / CPU;
-            for (int i = tid; i < n * nbt; i += nt) {
-                const int c = i % CPU, g = i / CPU;  // g = (j2 * npl + pl) * nr + r
-                const int jp = it.fnr.div(g), r = g - jp * nr;
-                const int j2 = it.fnpl.div(jp), pl = jp - j2 * npl;
-                H[((long long)(j2 * qu + it.t0 / CPU + pl) * B1 + it.k1 + r) * CPU + c] =
-                    buf[j2 * nbt + r * tn + pl * CPU + c];
+            for (int u = tid; u < n * nbt / CPU; u += nt) {
+                const int jp = fnr.div(u), r = u - jp * nr;
+                const int j2 = fnpl.div(jp), p = jp - j2 * npl;
+                Hu[(long long)(j2 * qu + t0 / CPU + p) * B1 + k1 + r] = bu[(j2 * nbt + r * tn) / CPU + p];
             }
         } else {
             for (int i = tid; i < n * nbt; i += nt) {
-                const int j2 = fnbt.div(i), cc = i - j2 * nbt, r = ftn.div(cc), t = it.t0 + cc - r * tn;
-                H[((long long)(j2 * qu + t / CPU) * B1 + it.k1 + r) * CPU + t % CPU] = buf[i];
+                const int j2 = fnbt.div(i), cc = i - j2 * nbt, r = ftn.div(cc), t = t0 + cc - r * tn;
+                H[((long long)(j2 * qu + t / CPU) * B1 + k1 + r) * CPU + t % CPU] = buf[i];
             }
         }
         __syncthreads();
@@ -237,24 +276,45 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
     const int z0 = pruned ? 2 * (B1 - B1 / 2) : B1 - B1 / 2, z1 = pruned ? n - 2 * (B1 / 2) : n - B1 / 2;
     for (int i = z0 * nb + tid; i < z1 * nb; i += nt)
         buf[i] = cmake<T>(0, 0);
-    const FastDiv &fnb = it.fnb, &fq = W.fq, &fb1 = W.fB1;
+    // copies, not references: the stores to G could alias the wedge record as
+    // far as the compiler knows, and it would reload them after every store
+    const FastDiv fnb = it.fnb, fnbu = it.fnbu, fq = W.fq, fb1 = W.fB1;
     const cplx<T> *H = a.H + (long long)b * a.H_stride + W.H_off;
     cplx<T> *G = a.G + (long long)b * a.G_stride + W.G_off;
     // H is plane-major (plane P = tau / CPU, element [(P * B1 + k1) * CPU + tau % CPU]): an item of
     // whole planes reads one contiguous block.  G is cell-major [j2][j1][rank], which keeps the
     // window columns that the interpolation stages contiguous over all ranks.
+    using U = typename Unit16<T>::type;
     constexpr int CPU = 16 / (int)sizeof(cplx<T>);
     const bool whole = nb % CPU == 0 && it.tau0 % CPU == 0;
     if (whole) {
-        // flat i = (p * B1 + k1) * CPU + c
-        const cplx<T> *src = H + (long long)it.tau0 * B1;
-        for (int i = tid; i < B1 * nb; i += nt) {
-            const int c = i % CPU, g = i / CPU;
-            const int p = fb1.div(g), k1 = g - p * B1;
-            int j1 = lo1 + k1;
-            if (j1 < 0)
-                j1 += n;
-            store_slot(buf, slot_code(pruned, j1, n, nb, p * CPU + c), nb, pruned, src[i]);
+        // 16-byte unit g = p * B1 + k1 holds ranks p * CPU .. p * CPU + CPU - 1 of box row k1, which
+        // land side by side in the buffer (nb and p * CPU are multiples of CPU); four loads in flight
+        const U *src = reinterpret_cast<const U *>(H + (long long)it.tau0 * B1);
+        U *bu = reinterpret_cast<U *>(buf);
+        const int tot = B1 * (nb / CPU);
+        constexpr int kIn = 4;
+        for (int g0 = tid; g0 < tot; g0 += kIn * nt) {
+            U v[kIn];
+            int code[kIn];
+#pragma unroll
+            for (int k = 0; k < kIn; ++k) {
+                const int g = g0 + k * nt < tot ? g0 + k * nt : g0;
+                v[k] = src[g];
+                const int p = fb1.div(g), k1 = g - p * B1;
+                int j1 = lo1 + k1;
+                if (j1 < 0)
+                    j1 += n;
+                code[k] = slot_code(pruned, j1, n, nb, p * CPU);
+            }
+#pragma unroll
+            for (int k = 0; k < kIn; ++k)
+                if (g0 + k * nt < tot) {
+                    const int pos = (code[k] >> 1) / CPU;
+                    bu[pos] = v[k];
+                    if (pruned)
+                        bu[pos + nb / CPU] = (code[k] & 1) ? neg_unit(v[k]) : v[k];
+                }
         }
     } else {
         // single ranks of one plane
@@ -271,10 +331,22 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
     fft_inplace<T, E>(buf, pl, n, nb, fnb, twl, tid, nt, pruned ? 1 : 0);
     // tau = j2 * q + t -> G[(j2 * n + j1) * q + t]; flat i = j1 * nb + c runs over the item's ranks
     // of a cell before the next cell
-    for (int i = tid; i < n * nb; i += nt) {
-        const int j1 = fnb.div(i), c = i - j1 * nb;
-        const int tau = it.tau0 + c, j2 = fq.div(tau), t = tau - j2 * q;
-        G[((long long)j2 * n + j1) * q + t] = buf[i];
+    if (whole) {
+        // unit u = j1 * (nb / CPU) + c / CPU: a rank pair (t even, q even) is one 16-byte store
+        const U *bu = reinterpret_cast<const U *>(buf);
+        U *Gu = reinterpret_cast<U *>(G);
+        const int nbu = nb / CPU;
+        for (int u = tid; u < n * nbu; u += nt) {
+            const int j1 = fnbu.div(u), c = (u - j1 * nbu) * CPU;
+            const int tau = it.tau0 + c, j2 = fq.div(tau), t = tau - j2 * q;
+            Gu[(((long long)j2 * n + j1) * q + t) / CPU] = bu[u];
+        }
+    } else {
+        for (int i = tid; i < n * nb; i += nt) {
+            const int j1 = fnb.div(i), c = i - j1 * nb;
+            const int tau = it.tau0 + c, j2 = fq.div(tau), t = tau - j2 * q;
+            G[((long long)j2 * n + j1) * q + t] = buf[i];
+        }
     }
 }
 
@@ -304,18 +376,6 @@ __global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(kCo
 // from the grid directly instead.  Up to kInterpBatch right-hand sides share
 // the warped point, the kernel weights and gamma^x.
 // ---------------------------------------------------------------------------
-// 16-byte unit of the staged window: two complex floats or one complex double.
-template <typename T>
-struct Unit16;
-template <>
-struct Unit16<float> {
-    using type = float4;
-};
-template <>
-struct Unit16<double> {
-    using type = double2;
-};
-
 // Row stride (16-byte units) of the staged window.  A ds_read_b128 serves 16
 // lanes of a wave per cycle from 64 four-byte banks, i.e. 16 unit residues:
 // two different cells whose unit addresses agree mod 16 cost an extra cycle,

@@ -911,11 +911,11 @@ fio_status plan_layout(fio_plan_s *P) {
             const long long npl = (long long)W.n[1] * qu;
             const int np = (int)std::min<long long>(npl, capc / plsz);
             for (long long p0 = 0; p0 < npl; p0 += np)
-                P->cols.push_back(make_col_item(l, (int)(p0 * cpu), (int)(std::min<long long>(np, npl - p0) * cpu)));
+                P->cols.push_back(make_col_item(l, (int)(p0 * cpu), (int)(std::min<long long>(np, npl - p0) * cpu), cpu));
             lds_cols = std::max(lds_cols, (size_t)(plsz * np + W.n[0]) * P->esize);  // buffer + twiddles
         } else {
             for (long long t0 = 0; t0 < (long long)W.n[1] * W.qpad; ++t0)
-                P->cols.push_back(make_col_item(l, (int)t0, 1));
+                P->cols.push_back(make_col_item(l, (int)t0, 1, cpu));
             lds_cols = std::max(lds_cols, (size_t)W.n[0] * 2 * P->esize);  // buffer + twiddles
         }
     }

@@ -55,12 +55,15 @@ struct RowItem {   // stage 1: box rows [k1, k1 + nr) of wedge ell, ranks [t0, t
 struct ColItem {   // stage 2: transforms tau in [tau0, tau0 + nb) of wedge ell (tau = j2 * q + t, plane tau / cpu)
     int l, tau0, nb, pad;
     FastDiv fnb;        // divider by nb
+    FastDiv fnbu;       // divider by nb / cpu (16-byte units per grid row of a whole-plane item)
 };
 inline RowItem make_row_item(int l, int k1, int nr, int t0, int tn, int cpu) {
     return RowItem{l,  k1, nr, t0, tn, 0, FastDiv((unsigned)tn), FastDiv((unsigned)(nr * tn)), FastDiv((unsigned)nr),
                    FastDiv((unsigned)std::max(1, tn / cpu))};
 }
-inline ColItem make_col_item(int l, int tau0, int nb) { return ColItem{l, tau0, nb, 0, FastDiv((unsigned)nb)}; }
+inline ColItem make_col_item(int l, int tau0, int nb, int cpu) {
+    return ColItem{l, tau0, nb, 0, FastDiv((unsigned)nb), FastDiv((unsigned)std::max(1, nb / cpu))};
+}
 
 // Kernel-side view of a plan (passed by value).
 template <typename T>
