@@ -442,6 +442,52 @@ __device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int l
     return F2 + best;
 }
 
+// Window of a tile's stencils on one wedge's grid from the sheared
+// coordinates of its points.  The coordinates are unwrapped around floor of
+// the smallest one, so the periodic wrap cannot split the window; the
+// stencil origin is monotone in the coordinate, so the bounds follow from
+// the extreme points with the same arithmetic.  Contains two block barriers
+// (the second, in pick_row_stride, also separates these reads of red from
+// the next call's writes).
+template <int W>
+__device__ __forceinline__ WinRec tile_window(bool active, double yp1, double yp2, int m1, int m2, int lane, int wave,
+                                              double (*red)[4], unsigned long long *red2) {
+    {
+        const double mn1 = wave_min(active ? yp1 : DBL_MAX), mx1 = wave_max(active ? yp1 : -DBL_MAX);
+        const double mn2 = wave_min(active ? yp2 : DBL_MAX), mx2 = wave_max(active ? yp2 : -DBL_MAX);
+        if (lane == 0) {
+            red[wave][0] = mn1;
+            red[wave][1] = mx1;
+            red[wave][2] = mn2;
+            red[wave][3] = mx2;
+        }
+    }
+    __syncthreads();
+    double lo1 = red[0][0], hi1 = red[0][1], lo2 = red[0][2], hi2 = red[0][3];
+#pragma unroll
+    for (int k = 1; k < kThreads / 64; ++k) {
+        lo1 = fmin(lo1, red[k][0]);
+        hi1 = fmax(hi1, red[k][1]);
+        lo2 = fmin(lo2, red[k][2]);
+        hi2 = fmax(hi2, red[k][3]);
+    }
+    const double k1 = floor(lo1), k2 = floor(lo2);
+    double u1, u2, ue;
+    const int j1 = stencil_origin<W>(m1, yp1, k1, u1), j2 = stencil_origin<W>(m2, yp2, k2, u2);
+    const int J1 = stencil_origin<W>(m1, lo1, k1, ue), X1 = stencil_origin<W>(m1, hi1, k1, ue);
+    const int J2 = stencil_origin<W>(m2, lo2, k2, ue), X2 = stencil_origin<W>(m2, hi2, k2, ue);
+    WinRec r;
+    r.J1 = J1;
+    r.J2 = J2;
+    r.F1 = X1 - J1 + W;
+    r.F2 = X2 - J2 + W;
+    r.S2 = pick_row_stride(active, j1 - J1, j2 - J2, r.F2, lane, wave, red2);
+    r.k1 = (int)k1;
+    r.k2 = (int)k2;
+    r.pad = 0;
+    return r;
+}
+
 // a += b * c as four fused multiply-adds
 template <typename T>
 __device__ __forceinline__ void cfma4(cplx<T> &a, cplx<T> b, cplx<T> c) {
@@ -521,7 +567,7 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
     __shared__ double red[kThreads / 64][4];
     __shared__ unsigned long long red2[kThreads / 64];
     const int N = a.N;
-    const int tiles2 = (N + kTileX - 1) / kTileX;
+    const int tiles2 = (N + kTileX - 1) / kTileX, ntiles = tiles2 * tiles2;
     const int T1 = (tile / tiles2) * kTileX, T2 = (tile % tiles2) * kTileX;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // a wave covers an 8 x 8 block of the tile and each 16-lane set that one
@@ -581,35 +627,22 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         psi -= rint(psi);
         T cs, sn;
         expi_t<T>(psi, cs, sn);
-        // Extent of the tile's points in the (unreduced) sheared coordinates.
-        // The tile's grid coordinates are unwrapped around floor of the
-        // smallest coordinate, so the periodic wrap cannot split its window;
-        // the stencil origin is monotone in the coordinate, so the window
-        // bounds follow from the extreme points with the same arithmetic.
-        {
-            const double mn1 = wave_min(active ? yp1 : DBL_MAX), mx1 = wave_max(active ? yp1 : -DBL_MAX);
-            const double mn2 = wave_min(active ? yp2 : DBL_MAX), mx2 = wave_max(active ? yp2 : -DBL_MAX);
-            if (lane == 0) {
-                red[wave][0] = mn1;
-                red[wave][1] = mx1;
-                red[wave][2] = mn2;
-                red[wave][3] = mx2;
+        // The tile's window on this wedge's grid: recorded at plan time by
+        // this same kernel (so from these very coordinates), or found here.
+        WinRec wr;
+        if (a.win_mode == kWinUse) {
+            wr = a.win[(long long)l * ntiles + tile];
+        } else {
+            wr = tile_window<W>(active, yp1, yp2, m1, m2, lane, wave, red, red2);
+            if (a.win_mode == kWinRecord) {
+                if (tid == 0)
+                    a.win[(long long)l * ntiles + tile] = wr;
+                continue;  // a recording launch interpolates nothing
             }
         }
-        __syncthreads();
-        double lo1 = red[0][0], hi1 = red[0][1], lo2 = red[0][2], hi2 = red[0][3];
-#pragma unroll
-        for (int k = 1; k < kThreads / 64; ++k) {
-            lo1 = fmin(lo1, red[k][0]);
-            hi1 = fmax(hi1, red[k][1]);
-            lo2 = fmin(lo2, red[k][2]);
-            hi2 = fmax(hi2, red[k][3]);
-        }
-        const double k1 = floor(lo1), k2 = floor(lo2);
-        double u1, u2, ue;
-        const int j1 = stencil_origin<W>(m1, yp1, k1, u1), j2 = stencil_origin<W>(m2, yp2, k2, u2);
-        const int J1 = stencil_origin<W>(m1, lo1, k1, ue), X1 = stencil_origin<W>(m1, hi1, k1, ue);
-        const int J2 = stencil_origin<W>(m2, lo2, k2, ue), X2 = stencil_origin<W>(m2, hi2, k2, ue);
+        double u1, u2;
+        const int j1 = stencil_origin<W>(m1, yp1, (double)wr.k1, u1), j2 = stencil_origin<W>(m2, yp2, (double)wr.k2, u2);
+        const int J1 = wr.J1, J2 = wr.J2;
         const T f1 = (T)(u1 - j1), f2 = (T)(u2 - j2);
         T w1[W], w2[W];
 #pragma unroll
@@ -628,9 +661,7 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                 for (int i2 = 0; i2 < W; ++i2)
                     w12[i1 * W + i2] = w1[i1] * w2[i2];
         }
-        const int F1 = X1 - J1 + W, F2 = X2 - J2 + W;
-        // the barrier in pick_row_stride also separates these reads of red from the next wedge's writes
-        const int S2 = pick_row_stride(active, j1 - J1, j2 - J2, F2, lane, wave, red2);
+        const int F1 = wr.F1, F2 = wr.F2, S2 = wr.S2;
         // The window of one rank-pair plane is F1 rows of S2 units (unit e =
         // rr * S2 + cc holds cell (J1 + rr, J2 + cc)), padded to whole 64-unit
         // wave chunks.  Rounds of planes are copied from G straight into LDS by
@@ -910,6 +941,8 @@ PlanArgs<T> make_args(const fio_plan_s *P) {
     a.zcol = static_cast<const double2 *>(P->d_zcol);
     a.zmat = static_cast<const double2 *>(P->d_zmat);
     a.zmat32 = static_cast<const float2 *>(P->d_zmat32);
+    a.win = P->d_win;
+    a.win_mode = P->d_win ? kWinUse : kWinCompute;
     return a;
 }
 
@@ -1120,6 +1153,10 @@ template <typename T>
 static void fill_inst_t(const fio_plan_s *P, const void *fhat, void *u, int B, void *out) {
     InstArgs<T> I;
     I.a = make_args<T>(P);
+    // the fused kernel is another compilation of the interpolation, whose
+    // coordinates need not round like those the table was recorded from
+    I.a.win = nullptr;
+    I.a.win_mode = kWinCompute;
     I.fhat = static_cast<const cplx<T> *>(fhat);
     I.u = static_cast<cplx<T> *>(u);
     I.B = B;
@@ -1147,11 +1184,41 @@ static hipError_t set_lds_limits_multi() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
 }
 
+// Record every tile's window on every wedge with the plan's own
+// interpolation kernel (a launch without right-hand sides).  Without the
+// table (it takes 32 bytes per tile and wedge) the kernel finds the windows
+// in every apply.
+template <typename T>
+static hipError_t record_windows(fio_plan_s *P) {
+    if (P->d_win) {
+        (void)hipFree(P->d_win);
+        P->d_win = nullptr;
+    }
+    const long long tiles = (P->N + kTileX - 1) / kTileX;
+    if (hipMalloc(&P->d_win, sizeof(WinRec) * (size_t)(tiles * tiles * P->L)) != hipSuccess) {
+        (void)hipGetLastError();
+        P->d_win = nullptr;
+        return hipSuccess;
+    }
+    PlanArgs<T> a = make_args<T>(P);
+    a.win_mode = kWinRecord;
+    hipError_t e = launch_interp<T>(P, a, nullptr, 0, 0, 0, 0, P->L, 0);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(0);
+    if (e != hipSuccess) {
+        (void)hipFree(P->d_win);
+        P->d_win = nullptr;
+    }
+    return e;
+}
+
 hipError_t apply_prepare(fio_plan_s *P) {
     hipError_t e = P->precision == FIO_F64 ? set_lds_limits<double>() : set_lds_limits<float>();
-    if (e != hipSuccess)
-        return e;
-    return P->precision == FIO_F64 ? set_lds_limits_multi<double>() : set_lds_limits_multi<float>();
+    if (e == hipSuccess)
+        e = P->precision == FIO_F64 ? set_lds_limits_multi<double>() : set_lds_limits_multi<float>();
+    if (e == hipSuccess)
+        e = P->precision == FIO_F64 ? record_windows<double>(P) : record_windows<float>(P);
+    return e;
 }
 
 hipError_t apply_launch(fio_plan_s *P, int B, const void *fhat, void *u, hipStream_t s, int l0, int l1) {

@@ -798,7 +798,7 @@ void release_layout(fio_plan_s *P) {
                      (void **)&P->d_map,    (void **)&P->d_omega,    &P->d_gxi,             &P->d_gx,
                      &P->d_tw,              &P->d_H,                 &P->d_G,               &P->d_zcol,
                      &P->d_zmat,            &P->d_zmat32,            (void **)&P->d_adj_bins, (void **)&P->d_adj_pts,
-                     (void **)&P->d_adj_ref};
+                     (void **)&P->d_adj_ref, (void **)&P->d_win};
     for (void **b : bufs) {
         if (*b)
             (void)hipFree(*b);

@@ -66,6 +66,17 @@ inline ColItem make_col_item(int l, int tau0, int nb, int cpu) {
 }
 
 // Kernel-side view of a plan (passed by value).
+// Interpolation window of one tile on one wedge's grid: first stencil cell
+// (J1, J2), extent F1 x F2, LDS row stride S2 (16-byte units) and the
+// integer reference (k1, k2) the tile's sheared coordinates are unwrapped
+// around.
+struct WinRec {
+    int J1, J2, F1, F2, S2, k1, k2, pad;
+};
+// How the interpolation finds its windows: from the tile's points (block
+// reductions), the same and recorded in the plan's table, or read from it.
+enum WinMode { kWinCompute = 0, kWinRecord = 1, kWinUse = 2 };
+
 template <typename T>
 struct PlanArgs {
     Phase phase;
@@ -84,6 +95,8 @@ struct PlanArgs {
     const double2 *zcol;           // regenerated factors (FIO_FACTORS_REGEN)
     const double2 *zmat;
     const float2 *zmat32;          // Z in FP32 (FP32 plans)
+    WinRec *win;                   // [wedge][tile] windows (WinMode)
+    int win_mode;
 };
 
 struct WedgeHost {
@@ -148,6 +161,7 @@ struct fio_plan_s {
     fio::AdjBin *d_adj_bins = nullptr;
     int *d_adj_pts = nullptr;
     int2 *d_adj_ref = nullptr;  // integer reference of every output tile and wedge
+    fio::WinRec *d_win = nullptr;  // interpolation window of every tile and wedge (recorded at plan time)
     int n_adj_bins = 0;
     long long n_adj_pts = 0;
     // optional per-stage event timing
