@@ -586,7 +586,9 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
     for (int b = 0; b < kInterpBatch; ++b)
         acc[b] = cmake<T>(0, 0);
     for (int l = l0; l < l1; ++l) {
-        const WedgeDev &wd = a.wedges[l];
+        // plan constants through the constant address space: scalar loads
+        // that run ahead, instead of vector loads waited on at every wedge
+        const WedgeDev wd = load_constant(a.wedges + l);
         if (wd.q == 0)
             continue;
         const int m1 = wd.n1, m2 = wd.n2, q = wd.q, qu = q / CPU;
@@ -631,7 +633,7 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         // this same kernel (so from these very coordinates), or found here.
         WinRec wr;
         if (a.win_mode == kWinUse) {
-            wr = a.win[(long long)l * ntiles + tile];
+            wr = load_constant(a.win + (long long)l * ntiles + tile);
         } else {
             wr = tile_window<W>(active, yp1, yp2, m1, m2, lane, wave, red, red2);
             if (a.win_mode == kWinRecord) {

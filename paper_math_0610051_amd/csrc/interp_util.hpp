@@ -70,6 +70,20 @@ __device__ __forceinline__ const __attribute__((address_space(4))) P *as_constan
     return (const __attribute__((address_space(4))) P *)(uintptr_t)p;
 }
 
+// A plan record (a multiple of 4 bytes) copied word by word through the
+// constant address space: scalar loads, of the words the caller uses only.
+template <typename S>
+__device__ __forceinline__ S load_constant(const S *p) {
+    static_assert(sizeof(S) % 4 == 0, "record of whole words");
+    S v;
+    const __attribute__((address_space(4))) unsigned *src = as_constant(reinterpret_cast<const unsigned *>(p));
+    unsigned *dst = reinterpret_cast<unsigned *>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(S) / 4); ++i)
+        dst[i] = src[i];
+    return v;
+}
+
 // FP32 regeneration of one point's separated factor (the storage-compressed
 // form of the randomized separation): sums over the sampled columns c <
 // zrc of A(x, C_c) Z(c, t), t < K, with each entry's phase in FP64, reduced

@@ -521,7 +521,7 @@ def copy(src, dst):
     return dst
 
 
-def autotune(N, phase, tol, params=(), B=1, precision="f32", max_tried=32):
+def autotune(N, phase, tol, params=(), B=1, precision="f32", max_tried=256):
     """fio_autotune: returns (best, tried) as dicts; best's fields map onto Plan keywords."""
     lib = load_library()
     ph = phase if isinstance(phase, fio_phase) else make_phase(phase, params)
