@@ -203,6 +203,7 @@ __global__ __launch_bounds__(kThreads) void k_spread(PlanArgs<T> a, const AdjBin
                                                      const cplx<T> *__restrict__ g, long long gstride, int B,
                                                      int bofs, int qstage) {
     constexpr int R = kStripRows<T>, C = kStripCols;
+    constexpr int CPU = 16 / (int)sizeof(cplx<T>);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int bi = blockIdx.x * (kThreads / 64) + wave;
     if (bi >= nbins)
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(kThreads) void k_spread(PlanArgs<T> a, const AdjBin
                         }
                 }
             }
-            // the strip's cells (G is [j2][j1][rank])
+            // the strip's cells (G is plane-major, g_index)
             if (lane < nb * tn) {
 #pragma unroll
                 for (int cc = 0; cc < C; ++cc) {
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_spread(PlanArgs<T> a, const AdjBin
                     for (int j = 0; j < R; ++j) {
                         const int gr = bin.o1 + j;
                         if (gr < m1 && gc < m2)
-                            G0[(long long)(b0 + bl) * a.G_stride + ((long long)gc * m1 + gr) * q + t0 + tl] =
+                            G0[(long long)(b0 + bl) * a.G_stride + g_index<CPU>(gr, gc, t0 + tl, m1, m2)] =
                                 acc[j][cc];
                     }
                 }
@@ -401,7 +402,7 @@ __global__ __launch_bounds__(kColThreads) void k_cols_adj(PlanArgs<T> a, const C
     for (int i = tid; i < n * nb; i += nt) {
         const int j1 = fnb.div(i), cc = i - j1 * nb;
         const int tau = it.tau0 + cc, j2 = fq.div(tau), t = tau - j2 * q;
-        buf[i] = cconj(G[((long long)j2 * n + j1) * q + t]);
+        buf[i] = cconj(G[g_index<CPU>(j1, j2, t, n, W.n2)]);
     }
     __syncthreads();
     fft_inplace<T, E>(buf, pl, n, nb, fnb, twl, tid, nt, 0);

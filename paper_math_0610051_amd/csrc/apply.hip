@@ -251,11 +251,12 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(kFf
 // ---------------------------------------------------------------------------
 // Stage 2: FFT along axis 1 (length n1, the long side) of nb transforms
 // tau = j2 * q + t, tau0 <= tau < tau0 + nb, of right-hand side b; rows
-// outside the box are the implicit zero padding.  Items hold whole cell
-// columns (nb a multiple of q, tau0 aligned) or a rank range of one column.
-// With H [j2][k1][rank] and G [j2][j1][rank] a whole-column item reads and
-// writes contiguous runs.  Many small workgroups per CU overlap one another's
-// load, transform and store phases.
+// outside the box are the implicit zero padding.  Items hold whole planes
+// (16-byte rank groups of a column: nb and tau0 multiples of CPU) or single
+// ranks of one plane.  H and G are both plane-major, so a whole-plane item
+// reads one contiguous block and writes one contiguous column per plane.
+// Many small workgroups per CU overlap one another's load, transform and
+// store phases.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it, int b) {
@@ -278,12 +279,13 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
         buf[i] = cmake<T>(0, 0);
     // copies, not references: the stores to G could alias the wedge record as
     // far as the compiler knows, and it would reload them after every store
-    const FastDiv fnb = it.fnb, fnbu = it.fnbu, fq = W.fq, fb1 = W.fB1;
+    const FastDiv fnb = it.fnb, fq = W.fq, fb1 = W.fB1, fn = W.fn1;
+    const int n2 = W.n2;
     const cplx<T> *H = a.H + (long long)b * a.H_stride + W.H_off;
     cplx<T> *G = a.G + (long long)b * a.G_stride + W.G_off;
     // H is plane-major (plane P = tau / CPU, element [(P * B1 + k1) * CPU + tau % CPU]): an item of
-    // whole planes reads one contiguous block.  G is cell-major [j2][j1][rank], which keeps the
-    // window columns that the interpolation stages contiguous over all ranks.
+    // whole planes reads one contiguous block.  G is plane-major too (g_index), which makes the
+    // window columns that the interpolation stages contiguous runs of each plane.
     using U = typename Unit16<T>::type;
     constexpr int CPU = 16 / (int)sizeof(cplx<T>);
     const bool whole = nb % CPU == 0 && it.tau0 % CPU == 0;
@@ -329,23 +331,23 @@ __device__ __forceinline__ void cols_body(const PlanArgs<T> &a, const ColItem it
     }
     __syncthreads();
     fft_inplace<T, E>(buf, pl, n, nb, fnb, twl, tid, nt, pruned ? 1 : 0);
-    // tau = j2 * q + t -> G[(j2 * n + j1) * q + t]; flat i = j1 * nb + c runs over the item's ranks
-    // of a cell before the next cell
+    // buffer element j1 * nb + c (transform tau = tau0 + c = j2 * q + t) -> G[g_index(j1, j2, t)]
     if (whole) {
-        // unit u = j1 * (nb / CPU) + c / CPU: a rank pair (t even, q even) is one 16-byte store
+        // one 16-byte unit per (plane, cell); consecutive threads take consecutive cells of a
+        // plane, so each plane's column leaves as one contiguous run
         const U *bu = reinterpret_cast<const U *>(buf);
         U *Gu = reinterpret_cast<U *>(G);
         const int nbu = nb / CPU;
         for (int u = tid; u < n * nbu; u += nt) {
-            const int j1 = fnbu.div(u), c = (u - j1 * nbu) * CPU;
-            const int tau = it.tau0 + c, j2 = fq.div(tau), t = tau - j2 * q;
-            Gu[(((long long)j2 * n + j1) * q + t) / CPU] = bu[u];
+            const int cu = fn.div(u), j1 = u - cu * n;
+            const int tau = it.tau0 + cu * CPU, j2 = fq.div(tau), t = tau - j2 * q;
+            Gu[((long long)(t / CPU) * n2 + j2) * n + j1] = bu[j1 * nbu + cu];
         }
     } else {
         for (int i = tid; i < n * nb; i += nt) {
             const int j1 = fnb.div(i), c = i - j1 * nb;
             const int tau = it.tau0 + c, j2 = fq.div(tau), t = tau - j2 * q;
-            G[((long long)j2 * n + j1) * q + t] = buf[i];
+            G[g_index<CPU>(j1, j2, t, n, n2)] = buf[i];
         }
     }
 }
@@ -376,22 +378,24 @@ __global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(kCo
 // from the grid directly instead.  Up to kInterpBatch right-hand sides share
 // the warped point, the kernel weights and gamma^x.
 // ---------------------------------------------------------------------------
-// Row stride (16-byte units) of the staged window.  A ds_read_b128 serves 16
-// lanes of a wave per cycle from 64 four-byte banks, i.e. 16 unit residues:
-// two different cells whose unit addresses agree mod 16 cost an extra cycle,
-// while lanes reading the same cell share it.  The 16 lanes of one cycle are
-// not a contiguous quarter of the wave: on gfx950 they are the four lane
-// quads that agree in lane bit 5 and in the parity of lane bits 2..4 (found
-// with bank-conflict counters over single-lane address probes).  Such a lane
-// set is closed under lane xor 1, 2, 12 and 24.  All lanes of one stencil
-// read are the lanes' base cells (d1, d2) shifted by a common offset, so the
-// conflicts follow from the base cells alone.  Each candidate stride
-// F2 .. F2 + 7 is scored per lane set by the number of distinct cells minus
-// the number of distinct residues, summed over the workgroup; the lowest
-// score wins, ties going to the smaller stride.  Lane sets whose cells spread
-// beyond 16 x 4 are not scored.  Contains one block barrier.
+// Column stride (16-byte units) of the staged window, which holds each plane
+// column-major: unit e = cc * S + rr is cell (J1 + rr, J2 + cc).  A
+// ds_read_b128 serves 16 lanes of a wave per cycle from 64 four-byte banks,
+// i.e. 16 unit residues: two different cells whose unit addresses agree mod
+// 16 cost an extra cycle, while lanes reading the same cell share it.  The 16
+// lanes of one cycle are not a contiguous quarter of the wave: on gfx950 they
+// are the four lane quads that agree in lane bit 5 and in the parity of lane
+// bits 2..4 (found with bank-conflict counters over single-lane address
+// probes).  Such a lane set is closed under lane xor 1, 2, 12 and 24.  All
+// lanes of one stencil read are the lanes' base cells (d1, d2) shifted by a
+// common offset, so the conflicts follow from the base cells alone.  Each
+// candidate stride F1 .. F1 + 7 is scored per lane set by the number of
+// distinct cells minus the number of distinct residues, summed over the
+// workgroup; the lowest score wins, ties going to the smaller stride.  Lane
+// sets whose cells spread beyond 8 x 8 are not scored.  Contains one block
+// barrier.
 constexpr int kPassXor[4] = {1, 2, 12, 24};  // generators of one ds_read_b128 lane set
-__device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int lane, int wave,
+__device__ inline int pick_col_stride(bool active, int d1, int d2, int F1, int lane, int wave,
                                       unsigned long long *red2) {
     int m1 = active ? d1 : INT_MAX, m2 = active ? d2 : INT_MAX;
 #pragma unroll
@@ -400,8 +404,8 @@ __device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int l
         m2 = min(m2, __shfl_xor(m2, kPassXor[k]));
     }
     const int e1 = active ? d1 - m1 : 0, e2 = active ? d2 - m2 : 0;
-    const bool fits = e1 < 16 && e2 < 4;
-    unsigned long long cell = (active && fits) ? 1ull << (e1 * 4 + e2) : 0ull;
+    const bool fits = e1 < 8 && e2 < 8;
+    unsigned long long cell = (active && fits) ? 1ull << (e2 * 8 + e1) : 0ull;
     int wide = fits ? 0 : 1;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -412,7 +416,7 @@ __device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int l
     unsigned long long packed = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        unsigned key = active ? 1u << ((e1 * (F2 + k) + e2) & 15) : 0u;
+        unsigned key = active ? 1u << ((e2 * (F1 + k) + e1) & 15) : 0u;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             key |= __shfl_xor(key, kPassXor[j]);
@@ -439,7 +443,7 @@ __device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int l
             best = k;
         }
     }
-    return F2 + best;
+    return F1 + best;
 }
 
 // Window of a tile's stencils on one wedge's grid from the sheared
@@ -447,7 +451,7 @@ __device__ inline int pick_row_stride(bool active, int d1, int d2, int F2, int l
 // the smallest one, so the periodic wrap cannot split the window; the
 // stencil origin is monotone in the coordinate, so the bounds follow from
 // the extreme points with the same arithmetic.  Contains two block barriers
-// (the second, in pick_row_stride, also separates these reads of red from
+// (the second, in pick_col_stride, also separates these reads of red from
 // the next call's writes).
 template <int W>
 __device__ __forceinline__ WinRec tile_window(bool active, double yp1, double yp2, int m1, int m2, int lane, int wave,
@@ -481,7 +485,7 @@ __device__ __forceinline__ WinRec tile_window(bool active, double yp1, double yp
     r.J2 = J2;
     r.F1 = X1 - J1 + W;
     r.F2 = X2 - J2 + W;
-    r.S2 = pick_row_stride(active, j1 - J1, j2 - J2, r.F2, lane, wave, red2);
+    r.S = pick_col_stride(active, j1 - J1, j2 - J2, r.F1, lane, wave, red2);
     r.k1 = (int)k1;
     r.k2 = (int)k2;
     r.pad = 0;
@@ -663,14 +667,16 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                 for (int i2 = 0; i2 < W; ++i2)
                     w12[i1 * W + i2] = w1[i1] * w2[i2];
         }
-        const int F1 = wr.F1, F2 = wr.F2, S2 = wr.S2;
-        // The window of one rank-pair plane is F1 rows of S2 units (unit e =
-        // rr * S2 + cc holds cell (J1 + rr, J2 + cc)), padded to whole 64-unit
-        // wave chunks.  Rounds of planes are copied from G straight into LDS by
-        // global_load_lds (lane i of a wave writes unit 64 c + i of chunk c):
-        // with two buffers the next round's copies run under the current
+        const int F1 = wr.F1, F2 = wr.F2, S = wr.S;
+        // The window of one plane (a rank pair in FP32) is F2 columns of S
+        // units (unit e = cc * S + rr holds cell (J1 + rr, J2 + cc)), padded
+        // to whole 64-unit wave chunks.  Rounds of planes are copied from G
+        // straight into LDS by global_load_lds (lane i of a wave writes unit
+        // 64 c + i of chunk c); a window column of a plane is one contiguous
+        // run of G, so consecutive lanes read consecutive 16-byte units.
+        // With two buffers the next round's copies run under the current
         // round's interpolation, with one a round is copied, then used.
-        const int units = F1 * S2;
+        const int units = F2 * S;
         const int planeP = (units + 63) & ~63;
         const int nbuf = 2 * planeP <= kUnits ? 2 : 1;
         const int bufU = kUnits / nbuf / 64 * 64;
@@ -682,38 +688,38 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
         const cplx<T> mod = cmake(cs, sn);
         const cplx<T> *G0 = a.G + (long long)bofs * a.G_stride + wd.G_off;
         if (staged) {
-            // source offsets (rank 0) of this thread's units tid + k kThreads;
-            // padding units copy cell 0 of the plane.  J1 > -W and J1 + F1 <=
-            // 2 m1 (likewise for axis 2), so one conditional wrap brings every
-            // window cell onto the grid (G is [j2][j1][rank])
+            // source offsets (16-byte units within a plane) of this thread's
+            // units tid + k kThreads; padding units copy cell 0 of the plane.
+            // J1 > -W and J1 + F1 <= 2 m1 (likewise for axis 2), so one
+            // conditional wrap brings every window cell onto the grid
             int off[kOff];
             const int c0 = J2 < 0 ? J2 + m2 : (J2 >= m2 ? J2 - m2 : J2);
             const int r0 = J1 < 0 ? J1 + m1 : (J1 >= m1 ? J1 - m1 : J1);
-            const float rS2 = 1.0f / (float)S2;
+            const float rS = 1.0f / (float)S;
 #pragma unroll
             for (int k = 0; k < kOff; ++k) {
                 const int e = tid + k * kThreads;
                 off[k] = 0;
                 if (e < units) {
-                    // e / S2 for e < 2^11: the float quotient is off by at most one
-                    int rr = (int)((float)e * rS2);
-                    if (rr * S2 > e)
-                        --rr;
-                    else if ((rr + 1) * S2 <= e)
-                        ++rr;
-                    const int cc = e - rr * S2;
-                    if (cc < F2) {
+                    // e / S for e < 2^11: the float quotient is off by at most one
+                    int cc = (int)((float)e * rS);
+                    if (cc * S > e)
+                        --cc;
+                    else if ((cc + 1) * S <= e)
+                        ++cc;
+                    const int rr = e - cc * S;
+                    if (rr < F1) {
                         int gr = r0 + rr;
                         if (gr >= m1)
                             gr -= m1;
                         int gc = c0 + cc;
                         if (gc >= m2)
                             gc -= m2;
-                        off[k] = (gc * m1 + gr) * q;
+                        off[k] = gc * m1 + gr;
                     }
                 }
             }
-            const int base = active ? (j1 - J1) * S2 + (j2 - J2) : 0;
+            const int base = active ? (j2 - J2) * S + (j1 - J1) : 0;
             // stored gamma^x rows of the tile's points, copied into LDS
             // ([t / CPU][thread] units) with the first round; the interpolation
             // then never waits on a global load of its own
@@ -743,12 +749,13 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                         const int np = min(ppr, nplanes - r * ppr);
                         U *dst = win + (r & (nbuf - 1)) * bufU + wave * 64;
                         for (int k2 = 0; k2 < np; ++k2) {
-                            const cplx<T> *G = G0 + (long long)sb * a.G_stride + stl * CPU;
+                            const U *Gp = reinterpret_cast<const U *>(G0 + (long long)sb * a.G_stride) +
+                                          (long long)stl * m2 * m1;
 #pragma unroll
                             for (int k = 0; k < kOff; ++k)
                                 if (wave * 64 + k * kThreads < units)
                                     __builtin_amdgcn_global_load_lds(
-                                        reinterpret_cast<const void *>(G + off[k]),
+                                        reinterpret_cast<const void *>(Gp + off[k]),
                                         (__attribute__((address_space(3))) void *)(dst + k2 * planeP + k * kThreads), 16,
                                         0, 0);
                             if (++stl == qu) {
@@ -776,12 +783,14 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                             sum = make_float4(0.f, 0.f, 0.f, 0.f);
                         else
                             sum = make_double2(0.0, 0.0);
+                        // column by column (a window column is contiguous), one running pointer
                         if constexpr (k2D) {
+                            const U *pc = pw;
 #pragma unroll
-                            for (int i1 = 0; i1 < W; ++i1)
+                            for (int i2 = 0; i2 < W; ++i2, pc += S)
 #pragma unroll
-                                for (int i2 = 0; i2 < W; ++i2) {
-                                    const U g = pw[i1 * S2 + i2];
+                                for (int i1 = 0; i1 < W; ++i1) {
+                                    const U g = pc[i1];
                                     const T wk = w12[i1 * W + i2];
                                     sum.x += wk * g.x;
                                     sum.y += wk * g.y;
@@ -790,32 +799,33 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                                         sum.w += wk * g.w;
                                     }
                                 }
-                        } else
+                        } else {
+                            const U *pc = pw;
 #pragma unroll
-                        for (int i1 = 0; i1 < W; ++i1) {
-                            const U *pr = pw + i1 * S2;
-                            U rs = pr[0];
-                            rs.x *= w2[0];
-                            rs.y *= w2[0];
-                            if constexpr (CPU == 2) {
-                                rs.z *= w2[0];
-                                rs.w *= w2[0];
-                            }
-#pragma unroll
-                            for (int i2 = 1; i2 < W; ++i2) {
-                                const U g = pr[i2];
-                                rs.x += w2[i2] * g.x;
-                                rs.y += w2[i2] * g.y;
+                            for (int i2 = 0; i2 < W; ++i2, pc += S) {
+                                U cs = pc[0];
+                                cs.x *= w1[0];
+                                cs.y *= w1[0];
                                 if constexpr (CPU == 2) {
-                                    rs.z += w2[i2] * g.z;
-                                    rs.w += w2[i2] * g.w;
+                                    cs.z *= w1[0];
+                                    cs.w *= w1[0];
                                 }
-                            }
-                            sum.x += w1[i1] * rs.x;
-                            sum.y += w1[i1] * rs.y;
-                            if constexpr (CPU == 2) {
-                                sum.z += w1[i1] * rs.z;
-                                sum.w += w1[i1] * rs.w;
+#pragma unroll
+                                for (int i1 = 1; i1 < W; ++i1) {
+                                    const U g = pc[i1];
+                                    cs.x += w1[i1] * g.x;
+                                    cs.y += w1[i1] * g.y;
+                                    if constexpr (CPU == 2) {
+                                        cs.z += w1[i1] * g.z;
+                                        cs.w += w1[i1] * g.w;
+                                    }
+                                }
+                                sum.x += w2[i2] * cs.x;
+                                sum.y += w2[i2] * cs.y;
+                                if constexpr (CPU == 2) {
+                                    sum.z += w2[i2] * cs.z;
+                                    sum.w += w2[i2] * cs.w;
+                                }
                             }
                         }
                         const U gx = reinterpret_cast<const U *>(gxl)[ctl * kThreads + tid];
@@ -854,14 +864,13 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
                         int r1 = g1i + i1;
                         if (r1 >= m1)
                             r1 -= m1;
-                        const cplx<T> *row = G + (long long)r1 * q + t;
                         cplx<T> rs = cmake<T>(0, 0);
 #pragma unroll
                         for (int i2 = 0; i2 < W; ++i2) {
                             int r2 = g2i + i2;
                             if (r2 >= m2)
                                 r2 -= m2;
-                            const cplx<T> g = row[(long long)r2 * m1 * q];
+                            const cplx<T> g = G[g_index<CPU>(r1, r2, t, m1, m2)];
                             rs.re += w2[i2] * g.re;
                             rs.im += w2[i2] * g.im;
                         }

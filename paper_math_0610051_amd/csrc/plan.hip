@@ -891,7 +891,7 @@ fio_status plan_layout(fio_plan_s *P) {
         // H is plane-major: plane P = j2 * qu + t / cpu holds ranks
         // [cpu (t / cpu), cpu (t / cpu + 1)) of grid column j2, element
         // [(P * B1 + k1) * cpu + t % cpu] (cpu = complex per 16 bytes); G is
-        // cell-major, [(j2 * n1 + j1) * q + t].
+        // plane-major as well, [((P * n2 + j2) * n1 + j1) * cpu + t % cpu].
         const int cpu = (int)(16 / P->esize), qu = W.qpad / cpu;
         // stage-1 items: nr adjacent box rows and tn ranks (whole planes),
         // aiming at 8 or more rows so each (column, plane) leaves as a run of
@@ -911,11 +911,11 @@ fio_status plan_layout(fio_plan_s *P) {
             const long long npl = (long long)W.n[1] * qu;
             const int np = (int)std::min<long long>(npl, capc / plsz);
             for (long long p0 = 0; p0 < npl; p0 += np)
-                P->cols.push_back(make_col_item(l, (int)(p0 * cpu), (int)(std::min<long long>(np, npl - p0) * cpu), cpu));
+                P->cols.push_back(make_col_item(l, (int)(p0 * cpu), (int)(std::min<long long>(np, npl - p0) * cpu)));
             lds_cols = std::max(lds_cols, (size_t)(plsz * np + W.n[0]) * P->esize);  // buffer + twiddles
         } else {
             for (long long t0 = 0; t0 < (long long)W.n[1] * W.qpad; ++t0)
-                P->cols.push_back(make_col_item(l, (int)t0, 1, cpu));
+                P->cols.push_back(make_col_item(l, (int)t0, 1));
             lds_cols = std::max(lds_cols, (size_t)W.n[0] * 2 * P->esize);  // buffer + twiddles
         }
     }

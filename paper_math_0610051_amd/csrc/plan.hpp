@@ -33,12 +33,22 @@ struct WedgeDev {
     long long gxi_off;   // gamma^xi (deconvolved, 1/N folded in), nmem * q complex
     long long gx_off;    // gamma^x, N^2 * q complex
     long long H_off;     // per-RHS row-transformed box, plane-major [j2][plane][k1][rank in plane]: n2 * B1 * q complex
-    long long G_off;     // per-RHS oversampled grid, cell-major [j2][j1][rank]: n2 * n1 * q complex
+    long long G_off;     // per-RHS oversampled grid, plane-major [plane][j2][j1] (g_index): n2 * n1 * q complex
     FastDiv fq, fB1, fB2, fn1, fn2;  // dividers by q, B1, B2, n1, n2 (constants built on the host)
     long long zc_off;    // regenerated factors: sampled column frequencies (zrc of them)
     long long zm_off;    // and Z = V S^-1, zrc * q complex double (zero-padded ranks)
     int zrc, pad2;       // number of sampled columns (0 when gamma^x is stored)
 };
+
+// Position of element t of cell (j1, j2) in one wedge's oversampled grid G
+// (one right-hand side).  G is plane-major: plane P = t / CPU (CPU complex
+// per 16 bytes: a rank pair in FP32, one rank in FP64) holds the n2 columns
+// of n1 cells as 16-byte units, so a window column of one plane is one
+// contiguous run.
+template <int CPU>
+__host__ __device__ inline long long g_index(int j1, int j2, int t, int n1, int n2) {
+    return (((long long)(t / CPU) * n2 + j2) * n1 + j1) * CPU + t % CPU;
+}
 
 // One block of an oversampled grid for the adjoint's spreading: wedge l,
 // first cell (o1, o2), and its n points at pts[off ...].
@@ -55,23 +65,20 @@ struct RowItem {   // stage 1: box rows [k1, k1 + nr) of wedge ell, ranks [t0, t
 struct ColItem {   // stage 2: transforms tau in [tau0, tau0 + nb) of wedge ell (tau = j2 * q + t, plane tau / cpu)
     int l, tau0, nb, pad;
     FastDiv fnb;        // divider by nb
-    FastDiv fnbu;       // divider by nb / cpu (16-byte units per grid row of a whole-plane item)
 };
 inline RowItem make_row_item(int l, int k1, int nr, int t0, int tn, int cpu) {
     return RowItem{l,  k1, nr, t0, tn, 0, FastDiv((unsigned)tn), FastDiv((unsigned)(nr * tn)), FastDiv((unsigned)nr),
                    FastDiv((unsigned)std::max(1, tn / cpu))};
 }
-inline ColItem make_col_item(int l, int tau0, int nb, int cpu) {
-    return ColItem{l, tau0, nb, 0, FastDiv((unsigned)nb), FastDiv((unsigned)std::max(1, nb / cpu))};
-}
+inline ColItem make_col_item(int l, int tau0, int nb) { return ColItem{l, tau0, nb, 0, FastDiv((unsigned)nb)}; }
 
 // Kernel-side view of a plan (passed by value).
 // Interpolation window of one tile on one wedge's grid: first stencil cell
-// (J1, J2), extent F1 x F2, LDS row stride S2 (16-byte units) and the
+// (J1, J2), extent F1 x F2, LDS column stride S >= F1 (16-byte units) and the
 // integer reference (k1, k2) the tile's sheared coordinates are unwrapped
 // around.
 struct WinRec {
-    int J1, J2, F1, F2, S2, k1, k2, pad;
+    int J1, J2, F1, F2, S, k1, k2, pad;
 };
 // How the interpolation finds its windows: from the tile's points (block
 // reductions), the same and recorded in the plan's table, or read from it.
