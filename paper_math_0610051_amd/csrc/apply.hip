@@ -884,7 +884,7 @@ __device__ __forceinline__ void interp_body(const PlanArgs<T> &a, cplx<T> *__res
             }
         }
     }
-    if (active) {
+    if (active && a.win_mode != kWinRecord) {
 #pragma unroll
         for (int b = 0; b < kInterpBatch; ++b)
             if (b < B)
@@ -1125,8 +1125,15 @@ hipError_t zero_fill(void *ptr, size_t bytes, hipStream_t s) {
 }
 
 template <typename T, int W>
-static void launch_multi_w(const MultiLaunch &ml, hipStream_t s) {
+static void launch_multi_w(const MultiLaunch &ml, hipStream_t s, bool interp_only = false) {
     const InstArgs<T> *I = static_cast<const InstArgs<T> *>(ml.inst);
+    if (interp_only) {
+        if (ml.regen)
+            k_interp_multi<T, W, true><<<ml.ntiles, kThreads, ml.lds_interp, s>>>(I, ml.tiles);
+        else
+            k_interp_multi<T, W, false><<<ml.ntiles, kThreads, ml.lds_interp, s>>>(I, ml.tiles);
+        return;
+    }
     if (ml.nrows)
         k_rows_multi<T><<<ml.nrows, kFftThreads, ml.lds_rows, s>>>(I, ml.rows);
     if (ml.ncols)
@@ -1140,34 +1147,40 @@ static void launch_multi_w(const MultiLaunch &ml, hipStream_t s) {
 }
 
 template <typename T>
-static hipError_t launch_multi_t(const MultiLaunch &ml, hipStream_t s) {
+static hipError_t launch_multi_t(const MultiLaunch &ml, hipStream_t s, bool interp_only) {
     switch (ml.w) {
-    case 4: launch_multi_w<T, 4>(ml, s); break;
-    case 5: launch_multi_w<T, 5>(ml, s); break;
-    case 6: launch_multi_w<T, 6>(ml, s); break;
-    case 7: launch_multi_w<T, 7>(ml, s); break;
-    case 8: launch_multi_w<T, 8>(ml, s); break;
-    case 10: launch_multi_w<T, 10>(ml, s); break;
-    case 12: launch_multi_w<T, 12>(ml, s); break;
-    case 14: launch_multi_w<T, 14>(ml, s); break;
-    case 16: launch_multi_w<T, 16>(ml, s); break;
+    case 4: launch_multi_w<T, 4>(ml, s, interp_only); break;
+    case 5: launch_multi_w<T, 5>(ml, s, interp_only); break;
+    case 6: launch_multi_w<T, 6>(ml, s, interp_only); break;
+    case 7: launch_multi_w<T, 7>(ml, s, interp_only); break;
+    case 8: launch_multi_w<T, 8>(ml, s, interp_only); break;
+    case 10: launch_multi_w<T, 10>(ml, s, interp_only); break;
+    case 12: launch_multi_w<T, 12>(ml, s, interp_only); break;
+    case 14: launch_multi_w<T, 14>(ml, s, interp_only); break;
+    case 16: launch_multi_w<T, 16>(ml, s, interp_only); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t multi_launch(const MultiLaunch &ml, hipStream_t s) {
-    return ml.precision == FIO_F64 ? launch_multi_t<double>(ml, s) : launch_multi_t<float>(ml, s);
+    return ml.precision == FIO_F64 ? launch_multi_t<double>(ml, s, false) : launch_multi_t<float>(ml, s, false);
+}
+
+hipError_t multi_record_windows(const MultiLaunch &ml, hipStream_t s) {
+    if (!ml.ntiles)
+        return hipSuccess;
+    return ml.precision == FIO_F64 ? launch_multi_t<double>(ml, s, true) : launch_multi_t<float>(ml, s, true);
 }
 
 template <typename T>
-static void fill_inst_t(const fio_plan_s *P, const void *fhat, void *u, int B, void *out) {
+static void fill_inst_t(const fio_plan_s *P, const void *fhat, void *u, int B, WinRec *win, int win_mode, void *out) {
     InstArgs<T> I;
     I.a = make_args<T>(P);
-    // the fused kernel is another compilation of the interpolation, whose
-    // coordinates need not round like those the table was recorded from
-    I.a.win = nullptr;
-    I.a.win_mode = kWinCompute;
+    // the fused kernel is another compilation of the interpolation (of the
+    // widest width of the launch), so it records and reads windows of its own
+    I.a.win = win;
+    I.a.win_mode = win ? win_mode : kWinCompute;
     I.fhat = static_cast<const cplx<T> *>(fhat);
     I.u = static_cast<cplx<T> *>(u);
     I.B = B;
@@ -1178,11 +1191,11 @@ size_t inst_args_size(int precision) {
     return precision == FIO_F64 ? sizeof(InstArgs<double>) : sizeof(InstArgs<float>);
 }
 
-void fill_inst_args(const fio_plan_s *P, const void *fhat, void *u, int B, void *out) {
+void fill_inst_args(const fio_plan_s *P, const void *fhat, void *u, int B, WinRec *win, int win_mode, void *out) {
     if (P->precision == FIO_F64)
-        fill_inst_t<double>(P, fhat, u, B, out);
+        fill_inst_t<double>(P, fhat, u, B, win, win_mode, out);
     else
-        fill_inst_t<float>(P, fhat, u, B, out);
+        fill_inst_t<float>(P, fhat, u, B, win, win_mode, out);
 }
 
 template <typename T>

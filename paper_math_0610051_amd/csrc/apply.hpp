@@ -95,8 +95,13 @@ struct MultiLaunch {
     size_t lds_interp = 0;       // dynamic LDS of the interpolation launch
 };
 hipError_t multi_launch(const MultiLaunch &ml, hipStream_t s);
+// The fused interpolation alone, its instances' arguments in record mode:
+// fills each instance's window table (WinRec per tile and wedge).
+hipError_t multi_record_windows(const MultiLaunch &ml, hipStream_t s);
 size_t inst_args_size(int precision);
-void fill_inst_args(const fio_plan_s *P, const void *fhat, void *u, int B, void *out);
+// win: the instance's window table for the fused kernel (nullptr: windows
+// found in every launch), read or recorded as win_mode says.
+void fill_inst_args(const fio_plan_s *P, const void *fhat, void *u, int B, WinRec *win, int win_mode, void *out);
 
 hipError_t apply_prepare(fio_plan_s *P);
 // Kernel-side view of a plan (instantiated for float and double).

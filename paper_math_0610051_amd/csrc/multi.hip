@@ -5,7 +5,8 @@
 // cached in the first plan and replayed while the instance list (plans and
 // batch sizes) stays the same; new data pointers only refresh the argument
 // table.  Instances of different kernel widths share the launch of the
-// widest width.  Instance lists the fused path cannot take (mixed factor
+// widest width, whose interpolation records the windows of every instance
+// when the state is built.  Instance lists the fused path cannot take (mixed factor
 // modes, a batch larger than a plan's workspace, or one plan listed twice,
 // whose single workspace cannot hold two instances at once) run instance
 // after instance.
@@ -29,6 +30,8 @@ struct MultiState {
     MultiRowItem *d_rows = nullptr;
     MultiColItem *d_cols = nullptr;
     MultiTile *d_tiles = nullptr;
+    WinRec *d_win = nullptr;           // every instance's window table, recorded by the fused kernel
+    std::vector<long long> win_off;    // first record of instance i
     hipStream_t cap = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;  // recorded after each replay, on the caller's stream
@@ -40,7 +43,7 @@ struct MultiState {
             (void)hipGraphExecDestroy(exec);
         if (cap)
             (void)hipStreamDestroy(cap);
-        void *bufs[] = {d_inst, d_rows, d_cols, d_tiles};
+        void *bufs[] = {d_inst, d_rows, d_cols, d_tiles, d_win};
         for (void *b : bufs)
             if (b)
                 (void)hipFree(b);
@@ -150,6 +153,25 @@ static fio_status build_state(MultiState &st, int n, const fio_plan_t *plans, co
                              : (size_t)interp_window_bytes<float>(q) + interp_gx_lds_bytes<float>(q);
         st.ml.lds_interp = std::max(st.ml.lds_interp, b);
     }
+    // the fused interpolation records every instance's windows once (a
+    // launch of it alone, no right-hand sides written); its replays read them
+    {
+        long long total = 0;
+        st.win_off.assign(n, 0);
+        for (int i = 0; i < n; ++i) {
+            const long long t = (plans[i]->N + kTileX - 1) / kTileX;
+            st.win_off[i] = total;
+            total += t * t * plans[i]->L;
+        }
+        FIO_HIP_TRY(hipMalloc(&st.d_win, sizeof(WinRec) * (size_t)std::max<long long>(1, total)));
+        const size_t isz = inst_args_size(plans[0]->precision);
+        std::vector<unsigned char> host(isz * n);
+        for (int i = 0; i < n; ++i)
+            fill_inst_args(plans[i], nullptr, nullptr, 0, st.d_win + st.win_off[i], kWinRecord, host.data() + isz * i);
+        FIO_HIP_TRY(hipMemcpy(st.d_inst, host.data(), host.size(), hipMemcpyHostToDevice));
+        FIO_HIP_TRY(multi_record_windows(st.ml, 0));
+        FIO_HIP_TRY(hipStreamSynchronize(0));
+    }
     FIO_HIP_TRY(hipEventCreateWithFlags(&st.done, hipEventDisableTiming));
     // capture the three launches once
     FIO_HIP_TRY(hipStreamCreateWithFlags(&st.cap, hipStreamNonBlocking));
@@ -214,7 +236,7 @@ fio_status multi_apply(int n, const fio_plan_t *plans, const void *const *fhat, 
         const size_t isz = inst_args_size(owner->precision);
         std::vector<unsigned char> host(isz * n);
         for (int i = 0; i < n; ++i) {
-            fill_inst_args(plans[i], fhat[i], u[i], B[i], host.data() + isz * i);
+            fill_inst_args(plans[i], fhat[i], u[i], B[i], st->d_win + st->win_off[i], kWinUse, host.data() + isz * i);
             st->f[i] = fhat[i];
             st->u[i] = u[i];
         }

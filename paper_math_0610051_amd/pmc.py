@@ -5,7 +5,8 @@ WRITE_SIZE read the bytes the L2 fetched from and wrote to memory; their unit
 and coverage are calibrated here against the plain copy kernel k_copy16 of a
 known size that runs in the same process: factor = bytes it moved / counter
 reading.  A traffic record stores the digest of the kernel sources it was
-measured on, so a changed kernel invalidates it.
+measured on, so a changed kernel invalidates it; a record file holds one
+record per kernel and plan configuration.
 
     python -m paper_math_0610051_amd.pmc FETCH.csv WRITE.csv --copy-bytes B \
         --kernel k_interp --out record.json [--meta key=value ...]
@@ -93,18 +94,25 @@ def traffic_record(fetch_csv, write_csv, copy_bytes, kernel, meta=None):
     return rec
 
 
-def load_traffic(path, kernel, **expect):
-    """Traffic bytes per launch from a stored record, or None if absent or stale."""
+def _records(path):
+    """The records of a traffic file: {"records": [...]}, or one bare record."""
     if not path or not os.path.exists(path):
-        return None
+        return []
     with open(path) as f:
-        rec = json.load(f)
-    if rec.get("kernel") != kernel or rec.get("source_digest") != source_digest():
-        return None
-    for k, v in expect.items():
-        if rec.get(k) != v:
-            return None
-    return rec
+        data = json.load(f)
+    return data.get("records", []) if "records" in data else [data]
+
+
+def load_traffic(path, kernel, **expect):
+    """Traffic bytes per launch from the stored record of this kernel and plan
+    configuration (expect: N, B, L, sigma, ...), or None if absent or stale."""
+    digest = source_digest()
+    for rec in _records(path):
+        if rec.get("kernel") != kernel or rec.get("source_digest") != digest:
+            continue
+        if all(rec.get(k) == v for k, v in expect.items()):
+            return rec
+    return None
 
 
 def main():
@@ -125,8 +133,12 @@ def main():
             pass
         meta[k] = v
     rec = traffic_record(a.fetch_csv, a.write_csv, a.copy_bytes, a.kernel, meta)
+    # one record per kernel and plan configuration: a new one replaces the
+    # record of the same configuration, stale or not
+    key = lambda r: json.dumps({k: r.get(k) for k in ["kernel"] + sorted(meta)}, sort_keys=True)
+    recs = [r for r in _records(a.out) if key(r) != key(rec)] + [rec]
     with open(a.out, "w") as f:
-        json.dump(rec, f, indent=1)
+        json.dump({"records": recs}, f, indent=1)
     print(json.dumps(rec))
 
 

@@ -27,3 +27,14 @@ def test_traffic_record_is_rejected_when_stale(tmp_path):
     path.write_text(json.dumps(rec))
     assert pmc.load_traffic(str(path), "k_interp", N=1024) is None
     assert pmc.load_traffic(str(tmp_path / "missing.json"), "k_interp") is None
+
+
+def test_traffic_file_holds_one_record_per_configuration(tmp_path):
+    d = pmc.source_digest()
+    recs = [{"kernel": "k_interp", "source_digest": d, "traffic_bytes": 1.0, "sigma": 2.0, "kernel_width": 5},
+            {"kernel": "k_interp", "source_digest": d, "traffic_bytes": 2.0, "sigma": 1.5, "kernel_width": 6}]
+    path = tmp_path / "recs.json"
+    path.write_text(json.dumps({"records": recs}))
+    assert pmc.load_traffic(str(path), "k_interp", sigma=2.0, kernel_width=5)["traffic_bytes"] == 1.0
+    assert pmc.load_traffic(str(path), "k_interp", sigma=1.5, kernel_width=6)["traffic_bytes"] == 2.0
+    assert pmc.load_traffic(str(path), "k_interp", sigma=1.75, kernel_width=6) is None
