@@ -88,42 +88,115 @@ void partition_coronae(int N, std::vector<int> &ids, std::vector<double> &thetas
 }
 
 // ---------------------------------------------------------------------------
-// Geometry of one wedge: shear among {I, lower/upper unit shears}, minimal box.
+// Geometry of one wedge: an integer unimodular shear M and the smallest box of
+// the sheared members.  Every M with entries in [-2, 2] and determinant +-1
+// is a candidate (the box of the sheared members is that of their convex
+// hull).  A candidate is scored by the work it implies per rank and
+// right-hand side: the oversampled grid's cells times its FFT passes, plus
+// kWindowWeight times the staged interpolation windows, estimated over all
+// 16 x 16 output tiles as the tile's image under M^{-T} on the grid plus the
+// kernel width (the warp's own spread is left out).  kWindowWeight is the
+// measured cost of a staged window unit per transformed cell and pass.
 // ---------------------------------------------------------------------------
-static const int kShears[5][4] = {{1, 0, 0, 1}, {1, 0, 1, 1}, {1, 0, -1, 1}, {1, 1, 0, 1}, {1, -1, 0, 1}};
+constexpr int kShearMax = 2;
+constexpr double kWindowWeight = 0.34;
 
-void wedge_geometry(int N, WedgeHost &W) {
+static int fft_pass_count(int n) {
+    FftPlan pl;
+    fft_make_plan(n, pl);
+    return std::max(1, pl.npass - 1);  // the leading radix-2 pass is folded into the load
+}
+
+// Convex hull of lattice points (Andrew's monotone chain), counter-clockwise.
+static std::vector<std::pair<int, int>> hull_of(std::vector<std::pair<int, int>> pts) {
+    std::sort(pts.begin(), pts.end());
+    pts.erase(std::unique(pts.begin(), pts.end()), pts.end());
+    if (pts.size() < 3)
+        return pts;
+    auto cross = [](const std::pair<int, int> &o, const std::pair<int, int> &a, const std::pair<int, int> &b) {
+        return (long long)(a.first - o.first) * (b.second - o.second) -
+               (long long)(a.second - o.second) * (b.first - o.first);
+    };
+    std::vector<std::pair<int, int>> h(2 * pts.size());
+    size_t k = 0;
+    for (size_t i = 0; i < pts.size(); ++i) {
+        while (k >= 2 && cross(h[k - 2], h[k - 1], pts[i]) <= 0)
+            --k;
+        h[k++] = pts[i];
+    }
+    for (size_t i = pts.size() - 1, t = k + 1; i > 0; --i) {
+        while (k >= t && cross(h[k - 2], h[k - 1], pts[i - 1]) <= 0)
+            --k;
+        h[k++] = pts[i - 1];
+    }
+    h.resize(k - 1);
+    return h;
+}
+
+void wedge_geometry(int N, double sigma, int w, WedgeHost &W) {
     const int h = N / 2;
-    long long best = -1;
-    for (int c = 0; c < 5; ++c) {
-        const int *M = kShears[c];
-        int mn1 = 1 << 30, mx1 = -(1 << 30), mn2 = 1 << 30, mx2 = -(1 << 30);
-        for (int om : W.members) {
-            const int k1 = om / N - h, k2 = om % N - h;
-            const int a1 = M[0] * k1 + M[1] * k2, a2 = M[2] * k1 + M[3] * k2;
-            mn1 = std::min(mn1, a1);
-            mx1 = std::max(mx1, a1);
-            mn2 = std::min(mn2, a2);
-            mx2 = std::max(mx2, a2);
-        }
-        const long long area = (long long)(mx1 - mn1 + 1) * (mx2 - mn2 + 1);
-        if (best < 0 || area < best) {
-            best = area;
-            std::memcpy(W.M, M, sizeof(W.M));
-            W.B[0] = mx1 - mn1 + 1;
-            W.B[1] = mx2 - mn2 + 1;
-            W.xc[0] = mn1 + W.B[0] / 2;
-            W.xc[1] = mn2 + W.B[1] / 2;
-        }
+    std::vector<std::pair<int, int>> pts;
+    pts.reserve(W.members.size());
+    for (int om : W.members)
+        pts.emplace_back(om / N - h, om % N - h);
+    const std::vector<std::pair<int, int>> hull = hull_of(pts);
+    const double tiles = std::ceil(N / 16.0) * std::ceil(N / 16.0);
+    // entries tried in the order 0, 1, -1, 2, -2, and among equal costs the
+    // smallest entries win, so an unsheared wedge keeps the identity
+    int vals[2 * kShearMax + 1];
+    vals[0] = 0;
+    for (int v = 1; v <= kShearMax; ++v) {
+        vals[2 * v - 1] = v;
+        vals[2 * v] = -v;
     }
-    // axis 1 is the long side of the box (its FFT runs in the column stage);
-    // swapping the rows of M keeps it unimodular (determinant -1)
-    if (W.B[1] > W.B[0]) {
-        std::swap(W.M[0], W.M[2]);
-        std::swap(W.M[1], W.M[3]);
-        std::swap(W.B[0], W.B[1]);
-        std::swap(W.xc[0], W.xc[1]);
-    }
+    double best = -1;
+    int best_norm = 0;
+    for (int m0 : vals)
+        for (int m1 : vals)
+            for (int m2 : vals)
+                for (int m3 : vals) {
+                    const int det = m0 * m3 - m1 * m2;
+                    if (det != 1 && det != -1)
+                        continue;
+                    int M[4] = {m0, m1, m2, m3};
+                    int mn1 = 1 << 30, mx1 = -(1 << 30), mn2 = 1 << 30, mx2 = -(1 << 30);
+                    for (const auto &pq : hull) {
+                        const int a1 = M[0] * pq.first + M[1] * pq.second, a2 = M[2] * pq.first + M[3] * pq.second;
+                        mn1 = std::min(mn1, a1);
+                        mx1 = std::max(mx1, a1);
+                        mn2 = std::min(mn2, a2);
+                        mx2 = std::max(mx2, a2);
+                    }
+                    int B[2] = {mx1 - mn1 + 1, mx2 - mn2 + 1}, xc[2] = {mn1 + B[0] / 2, mn2 + B[1] / 2};
+                    // axis 1 is the long side of the box (its FFT runs in the column stage);
+                    // swapping the rows of M keeps it unimodular
+                    if (B[1] > B[0]) {
+                        std::swap(M[0], M[2]);
+                        std::swap(M[1], M[3]);
+                        std::swap(B[0], B[1]);
+                        std::swap(xc[0], xc[1]);
+                    }
+                    int n[2];
+                    for (int d = 0; d < 2; ++d)
+                        n[d] = fft_nice_size(std::max((int)std::ceil(sigma * B[d]), 2 * w));
+                    const double fft = (double)n[0] * n[1] * (fft_pass_count(n[0]) + fft_pass_count(n[1]));
+                    // a tile spans 16 / N of the unit square; row d of M^{-T} = column d of M^{-1}, and
+                    // |M^{-1}| has the entries of M up to order and sign
+                    const double s1 = std::abs(M[3]) + std::abs(M[2]), s2 = std::abs(M[1]) + std::abs(M[0]);
+                    const double f1 = s1 * 16.0 * n[0] / N + w, f2 = s2 * 16.0 * n[1] / N + w;
+                    const double win = std::ceil(f2 * (f1 + 2) / 64.0) * 64.0 * tiles;
+                    const double cost = fft + kWindowWeight * win;
+                    const int norm = std::abs(m0) + std::abs(m1) + std::abs(m2) + std::abs(m3);
+                    if (best < 0 || cost < best * (1 - 1e-12) || (cost <= best * (1 + 1e-12) && norm < best_norm)) {
+                        best = cost;
+                        best_norm = norm;
+                        std::memcpy(W.M, M, sizeof(W.M));
+                        W.B[0] = B[0];
+                        W.B[1] = B[1];
+                        W.xc[0] = xc[0];
+                        W.xc[1] = xc[1];
+                    }
+                }
     W.lo[0] = -(W.B[0] / 2);
     W.lo[1] = -(W.B[1] / 2);
     // inverse of a unimodular [[a, b], [c, d]]: [[d, -b], [-c, a]] / det
@@ -778,7 +851,7 @@ static fio_status plan_geometry(fio_plan_s *P) {
     for (WedgeHost &W : P->wedges) {
         if (W.members.empty())
             continue;
-        wedge_geometry(N, W);
+        wedge_geometry(N, P->sigma, P->w, W);
         for (int d = 0; d < 2; ++d) {
             W.n[d] = fft_nice_size(std::max((int)std::ceil(P->sigma * W.B[d]), 2 * P->w));
             W.fft[d] = fft_for(W.n[d]);

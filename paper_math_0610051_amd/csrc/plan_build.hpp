@@ -20,7 +20,7 @@ struct DeviceScratch {
 int default_wedge_count(int N, const Phase &ph);
 void partition_equiangular(int N, int L, std::vector<int> &ids, std::vector<double> &thetas);
 void partition_coronae(int N, std::vector<int> &ids, std::vector<double> &thetas);
-void wedge_geometry(int N, WedgeHost &W);
+void wedge_geometry(int N, double sigma, int w, WedgeHost &W);
 void es_parameters(double eps, double sigma, int forced_w, int &w, double &beta);
 double es_fourier(int w, double beta, double omega);
 zd host_residual(const Phase &ph, int N, long long p, double e1, double e2, double k1, double k2);

@@ -5,7 +5,8 @@ WRITE_SIZE read the bytes the L2 fetched from and wrote to memory; their unit
 and coverage are calibrated here against the plain copy kernel k_copy16 of a
 known size that runs in the same process: factor = bytes it moved / counter
 reading.  A traffic record stores the digest of the kernel sources it was
-measured on, so a changed kernel invalidates it; a record file holds one
+measured on (and of the plan layout, which sets the bytes), so a changed kernel
+invalidates it; a record file holds one
 record per kernel and plan configuration.
 
     python -m paper_math_0610051_amd.pmc FETCH.csv WRITE.csv --copy-bytes B \
@@ -20,7 +21,7 @@ import json
 import os
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-KERNEL_SOURCES = ("apply.hip", "apply.hpp", "common.hpp", "fft.hpp", "interp_util.hpp", "plan.hpp")
+KERNEL_SOURCES = ("apply.hip", "apply.hpp", "common.hpp", "fft.hpp", "interp_util.hpp", "plan.hpp", "plan.hip")
 
 
 def _code_only(text: str) -> str:
