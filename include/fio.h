@@ -173,7 +173,9 @@ void fio_default_options(fio_options *opt);
  * separation reads singular values off the FP64 Gram matrix of the sampled
  * columns), else FIO_ENOTSUP.  FIO_EACCURACY if a wedge's separation error
  * estimate stays above tol after the verification retries.  On success *out
- * owns device memory. */
+ * owns device memory, among it the interpolation window of every 16 x 16
+ * output tile on every wedge (32 bytes each), recorded once here so that the
+ * applies read it. */
 fio_status fio_plan(int N, const fio_phase *phase, const fio_amplitude *amp, double tol, fio_plan_t *out);
 fio_status fio_plan_ex(int N, const fio_phase *phase, const fio_amplitude *amp, double tol,
                        const fio_options *opt /* nullable */, fio_plan_t *out);
@@ -240,10 +242,13 @@ fio_status fio_apply_batch_noalloc(fio_plan_t plan, int B, const void *fhat, voi
  * arrays of device pointers).  All instances, wedges and right-hand sides run
  * in one launch of each stage; the launch sequence is captured into a HIP
  * graph that is replayed while the plans and batch sizes stay the same (new
- * pointers refresh its argument table).  Instances run one after another
- * instead when their kernel widths differ, B[i] exceeds plan i's max_batch,
- * or a plan appears more than once in the list (its one workspace cannot
- * hold two instances at once). */
+ * pointers refresh its argument table).  Instances of different kernel
+ * widths share the interpolation launch of the widest; its windows (32 bytes
+ * per output tile and wedge of every instance) are recorded when the graph is
+ * built and held with it.  Instances run one after another instead when their
+ * factor modes differ, B[i] exceeds plan i's max_batch, or a plan appears more
+ * than once in the list (its one workspace cannot hold two instances at
+ * once). */
 fio_status fio_apply_multi(int n, const fio_plan_t *plans, const void *const *fhat, void *const *u,
                            const int *B, void *stream);
 
