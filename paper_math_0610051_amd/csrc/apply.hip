@@ -372,11 +372,14 @@ __global__ __launch_bounds__(kColThreads) __attribute__((amdgpu_waves_per_eu(kCo
 // and loops over the wedges.  For one wedge the stencils of the tile cover a
 // small window of the oversampled grid.  The window is found by a block
 // min/max reduction, with grid coordinates unwrapped around the tile's corner
-// point so that the periodic wrap cannot split it; it is staged into LDS
-// with coalesced row copies and every thread interpolates its point from
-// LDS.  A window larger than the LDS budget (strongly folded warps) is read
-// from the grid directly instead.  Up to kInterpBatch right-hand sides share
-// the warped point, the kernel weights and gamma^x.
+// point so that the periodic wrap cannot split it; a launch without
+// right-hand sides records it per tile and wedge at plan time, and applies
+// read the record.  The window is staged into LDS plane by plane, each window
+// column one contiguous run of the plane-major G, and every thread
+// interpolates its point from LDS.  A window larger than the LDS budget
+// (strongly folded warps) is read from the grid directly instead.  Up to
+// kInterpBatch right-hand sides share the warped point, the kernel weights
+// and gamma^x.
 // ---------------------------------------------------------------------------
 // Column stride (16-byte units) of the staged window, which holds each plane
 // column-major: unit e = cc * S + rr is cell (J1 + rr, J2 + cc).  A
