@@ -72,8 +72,10 @@ def test_wedge_boxes_hold_their_sheared_members():
         sel = ids == ell
         a = M @ np.stack([k1[sel], k2[sel]]) - np.array(w["xi_c"])[:, None]
         for d in range(2):
-            assert a[d].min() >= w["lo"][d] and a[d].max() < w["lo"][d] + w["box"][d]
+            # the box is the sheared members' bounding box, centred: tight on both sides
+            assert a[d].min() == w["lo"][d] and a[d].max() == w["lo"][d] + w["box"][d] - 1
             assert w["fine"][d] >= 2 * w["box"][d]
+        assert w["box"][0] >= w["box"][1]  # axis 1 is the long side
 
 
 # ------------------------------------------------------------------ a3: warped points (FP64)
